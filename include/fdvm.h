@@ -1,0 +1,233 @@
+/*
+ * fdvm.h -- C ABI of the MI355X (gfx950) blob-detection filter bank of
+ * H. L. Kennedy, "Digital filters with vanishing moments for shape analysis"
+ * (arXiv:1912.07133).
+ *
+ * Pipeline per frame and scale s (Section 5 two-stage architecture):
+ *   blur      B_s = separable low-pass blur, x (rows) then y (columns):
+ *               fdvm_blur_iir -- repeated-pole IIR of Section 4.3 / Table IV,
+ *                                realised as the causal + anti-causal
+ *                                recursions of Eqs A6-A10 with the
+ *                                steady-state start of Eq A32;
+ *               fdvm_blur_fir -- non-recursive FIR of Eq A5 (coloured
+ *                                Savitzky-Golay, Section 4.2, or sampled
+ *                                Gaussian, Eqs 9 and 11);
+ *   highpass  V_s = sigma_s^2 (D20 + D02) from the Table I d = 2 taps
+ *             (and optionally D10, D01, D11 for the Hessian of Eq 26);
+ *   detect    strict local extrema of V over 3 x 3 pixels x adjacent scales,
+ *             thresholded, listed in (scale, y, x) order.
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major, element (y, x) at base[y * pitch + x]; pitches and
+ *     plane strides are in ELEMENTS of the buffer's type.  1 <= H <= 65535,
+ *     1 <= W <= 16384.  x runs left to
+ *     right, y top to bottom (Appendix, Eqs A7-A8).
+ *   - Device pointers are plain HIP device addresses; the caller owns every
+ *     buffer (inputs, outputs, workspace).  The library allocates no device
+ *     memory, keeps no pointer after returning and has no mutable global
+ *     state; calls on different streams are independent.
+ *   - Device work is enqueued on `stream` (a hipStream_t passed as void*;
+ *     NULL = the legacy default stream) and the call returns without waiting.
+ *     Argument errors are detected on the host before anything is enqueued;
+ *     launch errors are reported as FDVM_EDEVICE; faults inside kernels show
+ *     up at the caller's next synchronisation.
+ *   - Boundary extension FDVM_BC_REPLICATE holds edge pixels constant to
+ *     infinity (the recursions start in the steady state of Eq A32; the FIR
+ *     and the high-pass stage clamp); FDVM_BC_ZERO pads with zeros (the
+ *     paper's FIR start-up, Section 5).
+ */
+#ifndef FDVM_H
+#define FDVM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FDVM_OK = 0,
+    FDVM_EINVAL = -1,       /* invalid argument (null pointer, bad size/pitch/enum) */
+    FDVM_ERANGE = -2,       /* sigma / length outside the supported design range */
+    FDVM_ENOMEM = -3,       /* caller-provided buffer too small (taps, workspace) */
+    FDVM_EDEVICE = -4,      /* a HIP call failed */
+    FDVM_EOVERFLOW = -5,    /* more detections than the output capacity */
+    FDVM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+} fdvm_status;
+
+typedef enum {
+    FDVM_IIR_REPEATED_POLE = 0, /* Filter D, Section 4.3 (order K = 2 or 3)   */
+    FDVM_FIR_COLORED_SG = 1,    /* Filter C, Section 4.2 (Eqs 20-22)          */
+    FDVM_FIR_GAUSSIAN = 2       /* Filter A, Eqs 9c and 11                    */
+} fdvm_kind;
+
+typedef enum { FDVM_BC_REPLICATE = 0, FDVM_BC_ZERO = 1 } fdvm_boundary;
+
+typedef enum { FDVM_U16 = 0, FDVM_F32 = 1, FDVM_F16 = 2, FDVM_BF16 = 3 } fdvm_dtype;
+
+typedef enum { FDVM_FIR_DIRECT = 0, FDVM_FIR_TOEPLITZ_MFMA = 1 } fdvm_fir_algo;
+
+/* high-pass outputs (bit mask for fdvm_highpass `what`) */
+enum {
+    FDVM_HP_LAPLACIAN = 1, /* sigma^2 (D20 + D02) (or unnormalised, see below) */
+    FDVM_HP_D20 = 2,
+    FDVM_HP_D02 = 4,
+    FDVM_HP_D11 = 8,
+    FDVM_HP_D10 = 16,
+    FDVM_HP_D01 = 32
+};
+
+#define FDVM_MAX_SCALES 16   /* scales per blur / high-pass / detect call */
+#define FDVM_MAX_FIR_HALF 512
+
+/*
+ * One designed filter (one scale).  Produced by fdvm_filter_design.
+ * IIR (Section 4.3): the DE of Eq A10 is
+ *   y+(n) = sum_{m=1..K} bp[m] x(n-m) - sum_{m=1..K} ap[m] y+(n-m)
+ *   y-(n) = sum_{m=1..K} bp[m] x(n+m) - sum_{m=1..K} ap[m] y-(n+m)
+ *   y(n)  = y+(n) + y-(n) + b0 x(n)
+ * with ap[0] = 1, bp[0] = 0, all poles at p = exp(-1/sigma).
+ * FIR: `order` is the half-length K, ntaps = 2K + 1; the taps themselves are
+ * returned through fdvm_filter_design's `taps` argument.
+ */
+typedef struct {
+    int32_t kind;      /* fdvm_kind                                          */
+    int32_t order;     /* IIR: K (2 or 3); FIR: half-length K                */
+    double sigma;      /* scale parameter (pixels)                           */
+    double p;          /* IIR: repeated pole exp(-1/sigma); FIR: 0           */
+    double b0;         /* IIR: central coefficient; FIR: h(0)                */
+    double bp[4];      /* IIR: forward numerator, bp[0] = 0                  */
+    double ap[4];      /* IIR: forward denominator, ap[0] = 1                */
+    double side_gain;  /* IIR: B+(1)/A+(1) = (1 - b0)/2 (steady-state gain)  */
+    double omega_c;    /* coloured SG: cutoff of Eq 21 (3/sigma); else 0     */
+    int32_t ntaps;     /* FIR: 2K + 1; IIR: 0                                */
+    int32_t reserved;
+} fdvm_filter;
+
+/* One detection, produced by fdvm_detect_blobs. */
+typedef struct {
+    int32_t y, x;       /* pixel                                           */
+    int32_t scale;      /* scale index s into the plane stack               */
+    int32_t polarity;   /* +1 bright blob (minimum of V), -1 dark (maximum) */
+    float value;        /* V at the pixel                                   */
+} fdvm_blob;
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *fdvm_status_string(fdvm_status status);
+
+/*
+ * fdvm_filter_design -- host-only, pure function (Section 4).
+ *   kind = FDVM_IIR_REPEATED_POLE: order K in {2, 3}.  K = 3 is the closed form
+ *     of Table IV (L_D = 1, Lbar_pi = 2); K = 2 is the same constrained design
+ *     with one Nyquist constraint (unit dc gain, zero second moment,
+ *     H(pi) = 0).  sigma in [0.25, 4096].  `fir_half_len`, `taps`,
+ *     `taps_cap` are ignored (taps may be NULL).
+ *   kind = FDVM_FIR_COLORED_SG: Eq 20 solved in float64 with S from Eq 22,
+ *     omega_c = 3/sigma and dc constraints rho = [1, 0] (D = 3);
+ *     kind = FDVM_FIR_GAUSSIAN: Eq 9c sampled on m = -K..K, normalised by Eq 11.
+ *     Half-length K = fir_half_len if > 0, else ceil(3 sigma) (length
+ *     6 sigma + 1).  K must be in [1, FDVM_MAX_FIR_HALF]; sigma in [0.25, 1024].
+ *     taps (host, float64, capacity taps_cap >= 2K + 1) receives
+ *     h(-K), ..., h(K).  `order` argument ignored for FIR.
+ * Returns FDVM_EINVAL (null out, bad kind/order), FDVM_ERANGE (sigma or K out
+ * of range), FDVM_ENOMEM (taps too small).
+ */
+fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_half_len,
+                               fdvm_filter *out, double *taps, int taps_cap);
+
+/*
+ * fdvm_blur_iir -- separable repeated-pole IIR blur of one frame at nscales
+ * scales (Eqs A6-A10, x then y; Sections 2 and 5).
+ *   in        device, H x W elements of type dt, row pitch in_pitch (>= W)
+ *             (u16 and f32/f16/bf16 are converted to float on load; u16 is
+ *             exact for the 12-bit frames this is built for)
+ *   out       device float32, nscales planes; plane s, pixel (y, x) at
+ *             out[s * plane_stride + y * out_pitch + x]; out_pitch >= W,
+ *             plane_stride >= H * out_pitch.  Must not overlap `in`.
+ *   filters   host array of nscales IIR designs (fdvm_filter_design output);
+ *             each must be FDVM_IIR_REPEATED_POLE with the same order (2 or 3).
+ *   bc        boundary extension (see conventions).
+ *   The recursions run in float32 as a cascade of K first-order sections with
+ *   the pole rounded once to float32 and the output weights designed in
+ *   float64 for that rounded pole.
+ * Returns FDVM_EINVAL on bad arguments (H, W < 1, nscales outside
+ * [1, FDVM_MAX_SCALES], mixed orders, pitch/stride too small, null pointers),
+ * FDVM_EDEVICE if a launch fails.
+ */
+fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                          float *out, int64_t out_pitch, int64_t plane_stride,
+                          const fdvm_filter *filters, int nscales, fdvm_boundary bc,
+                          void *stream);
+
+/*
+ * fdvm_blur_fir -- separable FIR blur (Eq A5), x then y, nscales scales.
+ *   Same image arguments as fdvm_blur_iir.
+ *   taps      host float64 array: the taps of scale s are taps[tap_offset[s] ..
+ *             tap_offset[s] + 2 K_s], K_s = half_len[s] (h(-K)..h(K), as
+ *             written by fdvm_filter_design).  Taps must be symmetric.
+ *   half_len  host int32[nscales], each in [1, FDVM_MAX_FIR_HALF].
+ *   tap_offset host int32[nscales].
+ *   algo      FDVM_FIR_DIRECT (LDS-staged direct convolution, float32) or
+ *             FDVM_FIR_TOEPLITZ_MFMA (Toeplitz-block products on the matrix
+ *             cores, float32 accumulation).
+ *   ws, ws_bytes device workspace of at least
+ *             fdvm_workspace_bytes(FDVM_OP_BLUR_FIR, H, W, nscales, maxK) bytes
+ *             (holds tap tables and the row-pass intermediate).
+ * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM (workspace too small) /
+ * FDVM_EDEVICE.
+ */
+fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                          float *out, int64_t out_pitch, int64_t plane_stride,
+                          const double *taps, const int32_t *half_len, const int32_t *tap_offset,
+                          int nscales, fdvm_boundary bc, int algo,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/* workspace sizes */
+enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2 };
+
+/* Bytes of device workspace `op` needs for an H x W frame with nscales
+ * scales and maximum FIR half-length max_half_len (0 if unused). */
+size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len);
+
+/*
+ * fdvm_highpass -- Table I interpolating differences of blur planes with
+ * clamp-to-edge extension.  For each scale s and each bit in `what`
+ * (FDVM_HP_*, in increasing bit order) one output plane is written:
+ *   LAPLACIAN: norm_s (D20 + D02), norm_s = sigmas[s]^2 if normalize else 1
+ *   D20 = B(x+1) - 2B + B(x-1), D02 likewise along y,
+ *   D10 = (B(x+1) - B(x-1))/2, D01 likewise, D11 = D10 applied along y.
+ *   blur      device float32 planes (pitch, plane_stride as in blur_iir)
+ *   sigmas    host float64[nscales]
+ *   out       device float32; output plane j of scale s (j counts the set bits
+ *             of `what`) at out[(s * nout + j) * out_plane_stride + y * pitch + x]
+ *             where nout = number of bits set.  Must not overlap `blur`.
+ */
+fdvm_status fdvm_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                          int nscales, const double *sigmas, unsigned what, int normalize,
+                          float *out, int64_t out_plane_stride, void *stream);
+
+/*
+ * fdvm_detect_blobs -- multi-scale strict extrema of the response planes.
+ * A pixel (s, y, x) with border <= y < H - border, border <= x < W - border
+ * is a detection when V is strictly below every existing neighbour in the
+ * 3 x 3 x 3 block of (scale, y, x) offsets and V <= -tau (bright blob,
+ * polarity +1), or strictly above every neighbour and V >= tau (dark blob,
+ * polarity -1).  Neighbours outside the stack are ignored; ties never detect.
+ *   resp      device float32 planes (as blur_iir's out)
+ *   out_dev   device fdvm_blob[cap], filled in (scale, y, x) order
+ *   count_dev device int32[1]: receives the TRUE number of detections (may
+ *             exceed cap; only the first cap are written)
+ *   ws        device workspace >= fdvm_workspace_bytes(FDVM_OP_DETECT, ...)
+ * The call is asynchronous; the caller reads *count_dev after synchronising
+ * and treats count > cap as overflow.  tau >= 0, border >= 0.
+ */
+fdvm_status fdvm_detect_blobs(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                              int nscales, float tau, int border, fdvm_blob *out_dev, int32_t cap,
+                              int32_t *count_dev, void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FDVM_H */

@@ -1,0 +1,301 @@
+"""MI355X (gfx950) blob-detection filter bank of Kennedy, "Digital filters with
+vanishing moments for shape analysis" (arXiv:1912.07133).
+
+Thin Python binding of the C ABI in include/fdvm.h (libfdvm.so, built in-tree
+by ``paper_1912_07133_amd.build``).  Every step of the filter bank runs in the
+library's HIP kernels; this module only marshals arguments: PyTorch provides
+device memory and the current stream.  There is no CPU fallback -- importing
+works without the library, but every call raises if it is not built.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import re
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfdvm.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "fdvm.h")
+
+# enums (include/fdvm.h)
+OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EOVERFLOW, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN = 0, 1, 2
+BC_REPLICATE, BC_ZERO = 0, 1
+U16, F32, F16, BF16 = 0, 1, 2, 3
+FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
+HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
+OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT = 0, 1, 2
+MAX_SCALES = 16
+MAX_FIR_HALF = 512
+
+KINDS = {"iir": IIR_REPEATED_POLE, "sg": FIR_COLORED_SG, "colored_sg": FIR_COLORED_SG,
+         "gaussian": FIR_GAUSSIAN}
+BOUNDARIES = {"replicate": BC_REPLICATE, "zero": BC_ZERO}
+
+
+class FdvmError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)} ({status})")
+
+
+class Filter(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("order", ctypes.c_int32), ("sigma", ctypes.c_double),
+                ("p", ctypes.c_double), ("b0", ctypes.c_double), ("bp", ctypes.c_double * 4),
+                ("ap", ctypes.c_double * 4), ("side_gain", ctypes.c_double),
+                ("omega_c", ctypes.c_double), ("ntaps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class Blob(ctypes.Structure):
+    _fields_ = [("y", ctypes.c_int32), ("x", ctypes.c_int32), ("scale", ctypes.c_int32),
+                ("polarity", ctypes.c_int32), ("value", ctypes.c_float)]
+
+
+BLOB_BYTES = ctypes.sizeof(Blob)
+_lib = None
+
+
+def library_available() -> bool:
+    return os.path.exists(LIB_PATH)
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libfdvm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run python -m paper_1912_07133_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.fdvm_status_string.restype = ctypes.c_char_p
+        L.fdvm_status_string.argtypes = [ctypes.c_int]
+        L.fdvm_filter_design.restype = ctypes.c_int
+        L.fdvm_filter_design.argtypes = [ctypes.c_int, ctypes.c_int, dbl, ctypes.c_int,
+                                         ctypes.POINTER(Filter), ctypes.POINTER(dbl), ctypes.c_int]
+        L.fdvm_workspace_bytes.restype = ctypes.c_size_t
+        L.fdvm_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, ctypes.c_int, ctypes.c_int]
+        L.fdvm_blur_iir.restype = ctypes.c_int
+        L.fdvm_blur_iir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
+                                    ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, vp]
+        L.fdvm_blur_fir.restype = ctypes.c_int
+        L.fdvm_blur_fir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
+                                    ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
+        L.fdvm_highpass.restype = ctypes.c_int
+        L.fdvm_highpass.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.POINTER(dbl),
+                                    ctypes.c_uint, ctypes.c_int, vp, i64, vp]
+        L.fdvm_detect_blobs.restype = ctypes.c_int
+        L.fdvm_detect_blobs.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_float,
+                                        ctypes.c_int, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list:
+    """Entry points declared in include/fdvm.h."""
+    with open(HEADER) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(fdvm_[a-z_]+)\s*\(", text)))
+
+
+def status_string(status: int) -> str:
+    if _lib is None and not library_available():
+        return "library not built"
+    return lib().fdvm_status_string(status).decode()
+
+
+def _check(status: int, what: str):
+    if status != OK:
+        raise FdvmError(status, what)
+
+
+# ------------------------------------------------------------------ design
+
+def filter_design(kind: str | int, sigma: float, order: int = 3, fir_half_len: int = 0) -> dict:
+    """fdvm_filter_design.  Returns a dict with the DE coefficients (IIR) or the
+    taps h(-K..K) (FIR) as float64."""
+    k = KINDS[kind] if isinstance(kind, str) else int(kind)
+    f = Filter()
+    cap = 2 * MAX_FIR_HALF + 1
+    taps = (ctypes.c_double * cap)()
+    _check(lib().fdvm_filter_design(k, order, float(sigma), int(fir_half_len), ctypes.byref(f), taps, cap),
+           "fdvm_filter_design")
+    out = {"kind": f.kind, "order": f.order, "sigma": f.sigma, "p": f.p, "b0": f.b0,
+           "bp": list(f.bp), "ap": list(f.ap), "side_gain": f.side_gain, "omega_c": f.omega_c,
+           "ntaps": f.ntaps, "_struct": f}
+    if f.ntaps:
+        out["taps"] = np.array(taps[: f.ntaps], dtype=np.float64)
+    return out
+
+
+def workspace_bytes(op: int, H: int, W: int, nscales: int, max_half_len: int = 0) -> int:
+    return int(lib().fdvm_workspace_bytes(op, H, W, nscales, max_half_len))
+
+
+# ------------------------------------------------------------------ device calls
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(device) -> int:
+    torch = _torch()
+    return int(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype in (torch.uint16, torch.int16):
+        return U16
+    if t.dtype == torch.float16:
+        return F16
+    if t.dtype == torch.bfloat16:
+        return BF16
+    raise TypeError(f"unsupported image dtype {t.dtype}")
+
+
+def _frame(x):
+    torch = _torch()
+    if not x.is_cuda:
+        raise ValueError("frame must be a CUDA (HIP) tensor")
+    if x.dim() != 2:
+        raise ValueError("frame must be [H, W]")
+    if x.stride(1) != 1:
+        x = x.contiguous()
+    return x
+
+
+def blur_iir(x, sigmas: Sequence[float], order: int = 3, boundary: str = "replicate", out=None):
+    """Repeated-pole IIR blur (fdvm_blur_iir): [H, W] -> float32 [S, H, W]."""
+    torch = _torch()
+    x = _frame(x)
+    H, W = x.shape
+    S = len(sigmas)
+    filt = (Filter * S)()
+    for i, s in enumerate(sigmas):
+        _check(lib().fdvm_filter_design(IIR_REPEATED_POLE, order, float(s), 0, ctypes.byref(filt[i]), None, 0),
+               "fdvm_filter_design")
+    if out is None:
+        out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    _check(lib().fdvm_blur_iir(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(), out.stride(1),
+                               out.stride(0), filt, S, BOUNDARIES[boundary], _stream_ptr(x.device)),
+           "fdvm_blur_iir")
+    return out
+
+
+def fir_taps(kind: str, sigmas: Sequence[float], half_lens: Sequence[int] | None = None):
+    """Designs for fdvm_blur_fir: (taps float64 concatenated, half_len, offsets)."""
+    taps, half, off = [], [], []
+    pos = 0
+    for i, s in enumerate(sigmas):
+        K = 0 if half_lens is None else int(half_lens[i])
+        d = filter_design(kind, s, fir_half_len=K)
+        taps.append(d["taps"])
+        half.append(d["order"])
+        off.append(pos)
+        pos += d["ntaps"]
+    return np.concatenate(taps), np.array(half, dtype=np.int32), np.array(off, dtype=np.int32)
+
+
+def blur_fir(x, sigmas: Sequence[float], kind: str = "sg", half_lens: Sequence[int] | None = None,
+             boundary: str = "replicate", algo: int = FIR_DIRECT, out=None, workspace=None, taps=None):
+    """FIR blur (fdvm_blur_fir): [H, W] -> float32 [S, H, W].  `taps` may be a
+    precomputed (taps, half_len, offsets) triple (e.g. from fir_taps)."""
+    torch = _torch()
+    x = _frame(x)
+    H, W = x.shape
+    S = len(sigmas)
+    t, half, off = taps if taps is not None else fir_taps(kind, sigmas, half_lens)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    half = np.ascontiguousarray(half, dtype=np.int32)
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    if out is None:
+        out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    need = workspace_bytes(OP_BLUR_FIR, H, W, S, int(half.max()))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    _check(lib().fdvm_blur_fir(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(), out.stride(1),
+                               out.stride(0), t.ctypes.data_as(dp), half.ctypes.data_as(ip),
+                               off.ctypes.data_as(ip), S, BOUNDARIES[boundary], algo, workspace.data_ptr(),
+                               workspace.numel(), _stream_ptr(x.device)), "fdvm_blur_fir")
+    return out
+
+
+def highpass(blur, sigmas: Sequence[float], what: int = HP_LAPLACIAN, normalize: bool = True, out=None):
+    """fdvm_highpass on float32 planes [S, H, W] -> [S, nout, H, W] (nout =
+    number of bits in `what`; squeezed to [S, H, W] when nout == 1)."""
+    torch = _torch()
+    if blur.dim() == 2:
+        blur = blur[None]
+    blur = blur.contiguous()  # output planes share the input pitch
+    S, H, W = blur.shape
+    nout = bin(what).count("1")
+    if out is None:
+        out = torch.empty((S, nout, H, W), dtype=torch.float32, device=blur.device)
+    sig = (ctypes.c_double * S)(*[float(s) for s in sigmas])
+    _check(lib().fdvm_highpass(blur.data_ptr(), H, W, blur.stride(1), blur.stride(0), S, sig, what,
+                               1 if normalize else 0, out.data_ptr(), out.stride(1), _stream_ptr(blur.device)),
+           "fdvm_highpass")
+    return out[:, 0] if nout == 1 else out
+
+
+def detect_blobs(resp, tau: float, border: int = 1, cap: int = 1 << 20, workspace=None, count_only=False):
+    """fdvm_detect_blobs on float32 planes [S, H, W].  Returns an int/float
+    numpy structured array (y, x, scale, polarity, value) in (scale, y, x)
+    order.  Raises FdvmError(EOVERFLOW) if more than `cap` detections."""
+    torch = _torch()
+    if resp.dim() == 2:
+        resp = resp[None]
+    resp = resp.contiguous()
+    S, H, W = resp.shape
+    dev = resp.device
+    buf = torch.empty(max(cap, 1) * BLOB_BYTES, dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(1, dtype=torch.int32, device=dev)
+    need = workspace_bytes(OP_DETECT, H, W, S)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(lib().fdvm_detect_blobs(resp.data_ptr(), H, W, resp.stride(1), resp.stride(0), S, float(tau),
+                                   int(border), buf.data_ptr(), int(cap), cnt.data_ptr(), workspace.data_ptr(),
+                                   workspace.numel(), _stream_ptr(dev)), "fdvm_detect_blobs")
+    n = int(cnt.item())
+    if n > cap:
+        raise FdvmError(EOVERFLOW, f"fdvm_detect_blobs: {n} detections > cap {cap}")
+    if count_only:
+        return n
+    raw = buf[: n * BLOB_BYTES].cpu().numpy()
+    dt = np.dtype([("y", np.int32), ("x", np.int32), ("scale", np.int32), ("polarity", np.int32),
+                   ("value", np.float32)])
+    return raw.view(dt).copy()
+
+
+def detect(frame, sigmas: Sequence[float], tau: float, kind: str = "iir", order: int = 3,
+           boundary: str = "replicate", border: int = 1, cap: int = 1 << 20, algo: int = FIR_DIRECT):
+    """The whole filter bank: blur (IIR or FIR) -> normalised Laplacian ->
+    multi-scale extrema.  Returns (blob list, Laplacian planes)."""
+    if kind == "iir":
+        B = blur_iir(frame, sigmas, order=order, boundary=boundary)
+    else:
+        B = blur_fir(frame, sigmas, kind=kind, boundary=boundary, algo=algo)
+    V = highpass(B, sigmas, HP_LAPLACIAN, True)
+    return detect_blobs(V, tau, border, cap), V
+
+
+def scale_of(sigma: float) -> float:
+    """Blob scale lambda = 2 sigma (Section 5)."""
+    return 2.0 * sigma
+
+
+__all__ = ["filter_design", "blur_iir", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
+           "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of"]
+_ = math

@@ -1,0 +1,216 @@
+// C ABI of the blob-detection filter bank: argument validation on the host,
+// then dispatch to the HIP kernels.  See include/fdvm.h for the contract.
+#include <cmath>
+#include <cstring>
+
+#include "fdvm_internal.h"
+
+using namespace fdvm;
+
+namespace {
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+fdvm_status from_hip(hipError_t e) { return e == hipSuccess ? FDVM_OK : FDVM_EDEVICE; }
+
+fdvm_status check_image(const void *in, int64_t H, int64_t W, int64_t in_pitch) {
+    if (!in) return FDVM_EINVAL;
+    if (H < 1 || W < 1 || H > 65535 || W > 16384) return FDVM_EINVAL;
+    if (in_pitch < W) return FDVM_EINVAL;
+    return FDVM_OK;
+}
+
+fdvm_status check_planes(const void *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                         int nscales) {
+    if (!out) return FDVM_EINVAL;
+    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
+    if (pitch < W) return FDVM_EINVAL;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    if (nscales == 1 && plane_stride < 0) return FDVM_EINVAL;
+    return FDVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fdvm_status_string(fdvm_status s) {
+    switch (s) {
+        case FDVM_OK: return "ok";
+        case FDVM_EINVAL: return "invalid argument";
+        case FDVM_ERANGE: return "parameter out of the supported range";
+        case FDVM_ENOMEM: return "buffer too small";
+        case FDVM_EDEVICE: return "HIP device error";
+        case FDVM_EOVERFLOW: return "detection list overflow";
+        case FDVM_EUNSUPPORTED: return "not supported";
+    }
+    return "unknown status";
+}
+
+fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_half_len,
+                               fdvm_filter *out, double *taps, int taps_cap) {
+    if (!out) return FDVM_EINVAL;
+    if (!std::isfinite(sigma)) return FDVM_ERANGE;
+    fdvm_filter f;
+    std::memset(&f, 0, sizeof(f));
+    f.kind = kind;
+    f.sigma = sigma;
+    if (kind == FDVM_IIR_REPEATED_POLE) {
+        if (order != 2 && order != 3) return FDVM_EINVAL;
+        if (!(sigma >= 0.25 && sigma <= 4096.0)) return FDVM_ERANGE;
+        f.order = order;
+        f.p = std::exp(-1.0 / sigma);
+        const double e = -std::expm1(-1.0 / sigma);  // 1 - p to full relative precision
+        double b0, bp[4], ap[4];
+        repeated_pole_de(order, f.p, e, &b0, bp, ap);
+        f.b0 = b0;
+        for (int m = 0; m < 4; ++m) {
+            f.bp[m] = bp[m];
+            f.ap[m] = ap[m];
+        }
+        f.side_gain = 0.5 * (1.0 - b0);
+        *out = f;
+        return FDVM_OK;
+    }
+    if (kind == FDVM_FIR_COLORED_SG || kind == FDVM_FIR_GAUSSIAN) {
+        if (!(sigma >= 0.25 && sigma <= 1024.0)) return FDVM_ERANGE;
+        const int K = fir_half_len > 0 ? fir_half_len : (int)std::ceil(3.0 * sigma - 1e-9);
+        if (K < 1 || K > FDVM_MAX_FIR_HALF) return FDVM_ERANGE;
+        if (!taps) return FDVM_EINVAL;
+        if (taps_cap < 2 * K + 1) return FDVM_ENOMEM;
+        f.order = K;
+        f.ntaps = 2 * K + 1;
+        int rc;
+        if (kind == FDVM_FIR_COLORED_SG) {
+            f.omega_c = 3.0 / sigma;
+            rc = colored_sg_taps(sigma, K, f.omega_c, taps);
+        } else {
+            rc = gaussian_taps(sigma, K, taps);
+        }
+        if (rc != 0) return FDVM_ERANGE;
+        f.b0 = taps[K];
+        *out = f;
+        return FDVM_OK;
+    }
+    return FDVM_EINVAL;
+}
+
+size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len) {
+    if (H < 1 || W < 1 || nscales < 1) return 0;
+    switch (op) {
+        case FDVM_OP_BLUR_IIR: return 0;
+        case FDVM_OP_BLUR_FIR: return fir_workspace_bytes(H, W, nscales, max_half_len);
+        case FDVM_OP_DETECT: return detect_workspace_bytes(H, W, nscales);
+        default: return 0;
+    }
+}
+
+fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                          int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
+                          fdvm_boundary bc, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (!filters) return FDVM_EINVAL;
+    if (dt != FDVM_U16 && dt != FDVM_F32 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
+    if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
+    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+    const int order = filters[0].order;
+    if (order != 2 && order != 3) return FDVM_EINVAL;
+    IirParams prm;
+    std::memset(&prm, 0, sizeof(prm));
+    prm.nscales = nscales;
+    prm.order = order;
+    prm.boundary = bc;
+    for (int s = 0; s < nscales; ++s) {
+        const fdvm_filter &f = filters[s];
+        if (f.kind != FDVM_IIR_REPEATED_POLE || f.order != order) return FDVM_EINVAL;
+        if (!(f.sigma >= 0.25 && f.sigma <= 4096.0)) return FDVM_ERANGE;
+        const Cascade c = cascade_realisation(order, f.sigma);
+        IirScaleParams &q = prm.s[s];
+        q.p = c.p;
+        q.b0 = c.b0;
+        for (int k = 0; k < 3; ++k) {
+            q.w[k] = c.w[k];
+            q.ss[k] = c.ss[k];
+        }
+        q.lnp = c.lnp;
+        q.p_tile = (float)std::exp(IIR_TILE * c.lnp);
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs);
+    if (e != hipSuccess) return FDVM_EDEVICE;
+    e = launch_iir_cols(out, H, W, out_pitch, plane_stride, prm, hs);
+    return from_hip(e);
+}
+
+fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                          int64_t out_pitch, int64_t plane_stride, const double *taps, const int32_t *half_len,
+                          const int32_t *tap_offset, int nscales, fdvm_boundary bc, int algo, void *ws,
+                          size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (!taps || !half_len || !tap_offset || !ws) return FDVM_EINVAL;
+    if (dt != FDVM_U16 && dt != FDVM_F32 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
+    if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
+    if (algo != FDVM_FIR_DIRECT && algo != FDVM_FIR_TOEPLITZ_MFMA) return FDVM_EINVAL;
+    int maxK = 0;
+    for (int s = 0; s < nscales; ++s) {
+        if (half_len[s] < 1 || half_len[s] > FDVM_MAX_FIR_HALF) return FDVM_ERANGE;
+        if (tap_offset[s] < 0) return FDVM_EINVAL;
+        if (half_len[s] > maxK) maxK = half_len[s];
+        const double *h = taps + tap_offset[s];
+        const int K = half_len[s];
+        for (int m = 1; m <= K; ++m)
+            if (h[K + m] != h[K - m]) return FDVM_EINVAL;  // symmetric taps only
+    }
+    if (ws_bytes < fir_workspace_bytes(H, W, nscales, maxK)) return FDVM_ENOMEM;
+    if (algo == FDVM_FIR_TOEPLITZ_MFMA) {
+        if (!fir_mfma_available()) return FDVM_EUNSUPPORTED;
+    }
+    hipError_t e = launch_fir(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, taps, half_len, tap_offset,
+                              nscales, bc, algo, ws, ws_bytes, static_cast<hipStream_t>(stream));
+    return from_hip(e);
+}
+
+fdvm_status fdvm_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                          int nscales, const double *sigmas, unsigned what, int normalize, float *out,
+                          int64_t out_plane_stride, void *stream) {
+    fdvm_status st = check_image(blur, H, W, pitch);
+    if (st != FDVM_OK) return st;
+    if (!out || !sigmas) return FDVM_EINVAL;
+    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    if (what == 0 || (what & ~63u)) return FDVM_EINVAL;
+    int nout = 0;
+    for (unsigned b = what; b; b >>= 1) nout += (int)(b & 1u);
+    if ((nout > 1 || nscales > 1) && out_plane_stride < H * pitch) return FDVM_EINVAL;
+    float norms[FDVM_MAX_SCALES];
+    for (int s = 0; s < nscales; ++s) {
+        if (!finite_pos(sigmas[s])) return FDVM_ERANGE;
+        norms[s] = normalize ? (float)(sigmas[s] * sigmas[s]) : 1.0f;
+    }
+    hipError_t e = launch_highpass(blur, H, W, pitch, plane_stride, nscales, norms, what, out, out_plane_stride,
+                                   static_cast<hipStream_t>(stream));
+    return from_hip(e);
+}
+
+fdvm_status fdvm_detect_blobs(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                              int nscales, float tau, int border, fdvm_blob *out_dev, int32_t cap,
+                              int32_t *count_dev, void *ws, size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(resp, H, W, pitch);
+    if (st != FDVM_OK) return st;
+    if (!out_dev || !count_dev || !ws) return FDVM_EINVAL;
+    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    if (!(tau >= 0.0f) || !std::isfinite(tau) || border < 0 || cap < 0) return FDVM_EINVAL;
+    if (ws_bytes < detect_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
+    hipError_t e = launch_detect(resp, H, W, pitch, plane_stride, nscales, tau, border, out_dev, cap, count_dev,
+                                 ws, static_cast<hipStream_t>(stream));
+    return from_hip(e);
+}
+
+}  // extern "C"

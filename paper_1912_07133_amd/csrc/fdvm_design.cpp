@@ -1,0 +1,191 @@
+// Host-side filter design (float64) for the blob-detection filter bank.
+//
+//  * Repeated-pole IIR blur, Section 4.3 / Table IV (K = 3) and the same
+//    constrained design with a single Nyquist constraint (K = 2).  The Table IV
+//    polynomials are evaluated in factored form in terms of p and e = 1 - p so
+//    that nothing cancels as p -> 1 (coarse scales).
+//  * Float32 cascade realisation of the same transfer function.
+//  * Coloured Savitzky-Golay FIR (Section 4.2, Eqs 20-22) and sampled Gaussian
+//    FIR (Eqs 9c, 11).
+#include <cmath>
+#include <vector>
+
+#include "fdvm_internal.h"
+
+namespace fdvm {
+
+namespace {
+
+// DE coefficients of the repeated-pole blur at pole p (e = 1 - p supplied
+// separately so it keeps full relative precision).
+//
+// K = 3 (Table IV, factored):
+//   b0    = e (8 - p - p^2) / 16
+//   b+_1  = 3 e (1 + p) (3 - p^2) / 32
+//   b+_2  = -3 p e (1 + p) (5 - p^2) / 32
+//   b+_3  = -e (1 + p) (p^4 - 8 p^2 + 1) / 32
+//   a+    = [1, -3p, 3p^2, -p^3]
+// K = 2 (unit dc gain, zero 2nd moment, H(pi) = 0 on the basis
+//        {p^|m|, |m| p^|m|, delta(m)}):
+//   b0    = e (5 + p) / 8
+//   b+_1  = e (1 + p) (2 + p) / 8
+//   b+_2  = -e (1 + p) (p^2 + 4p + 1) / 16
+//   a+    = [1, -2p, p^2]
+void de_coefficients(int K, double p, double e, double *b0, double bp[4], double ap[4]) {
+    for (int i = 0; i < 4; ++i) bp[i] = ap[i] = 0.0;
+    ap[0] = 1.0;
+    const double q = 1.0 + p;
+    if (K == 3) {
+        *b0 = e * (8.0 - p - p * p) / 16.0;
+        bp[1] = 3.0 * e * q * (3.0 - p * p) / 32.0;
+        bp[2] = -3.0 * p * e * q * (5.0 - p * p) / 32.0;
+        bp[3] = -e * q * (p * p * p * p - 8.0 * p * p + 1.0) / 32.0;
+        ap[1] = -3.0 * p;
+        ap[2] = 3.0 * p * p;
+        ap[3] = -p * p * p;
+    } else {
+        *b0 = e * (5.0 + p) / 8.0;
+        bp[1] = e * q * (2.0 + p) / 8.0;
+        bp[2] = -e * q * (p * p + 4.0 * p + 1.0) / 16.0;
+        ap[1] = -2.0 * p;
+        ap[2] = p * p;
+    }
+}
+
+// Output weights of the cascade form.  With v_k = x / (1 - p z^-1)^k and
+// y+(n) = sum_k W_k v_k(n-1), matching B+(z) = sum_m b+_m z^-m gives
+//   K = 3: W_1 = -e (1+p)(p^4 - 8p^2 + 1) / (32 p^2)
+//          W_2 =  e^2 (1+p)^2 (p^2 + 2) / (32 p^2)
+//          W_3 = -e^3 (1+p)^3 / (32 p^2)
+//   K = 2: W_1 =  e (1+p)(p^2 + 4p + 1) / (16 p)
+//          W_2 = -e^2 (1+p)^2 / (16 p)
+void cascade_weights(int K, double p, double e, double W[3]) {
+    const double q = 1.0 + p;
+    W[0] = W[1] = W[2] = 0.0;
+    if (K == 3) {
+        W[0] = -e * q * (p * p * p * p - 8.0 * p * p + 1.0) / (32.0 * p * p);
+        W[1] = e * e * q * q * (p * p + 2.0) / (32.0 * p * p);
+        W[2] = -e * e * e * q * q * q / (32.0 * p * p);
+    } else {
+        W[0] = e * q * (p * p + 4.0 * p + 1.0) / (16.0 * p);
+        W[1] = -e * e * q * q / (16.0 * p);
+    }
+}
+
+}  // namespace
+
+void repeated_pole_de(int K, double p, double e, double *b0, double bp[4], double ap[4]) {
+    de_coefficients(K, p, e, b0, bp, ap);
+}
+
+Cascade cascade_realisation(int K, double sigma) {
+    Cascade c{};
+    const float p32 = static_cast<float>(std::exp(-1.0 / sigma));
+    const double p = static_cast<double>(p32);
+    const double e = 1.0 - p;  // exact: p32 and 1 are both doubles
+    double b0, bp[4], ap[4], W[3];
+    de_coefficients(K, p, e, &b0, bp, ap);
+    cascade_weights(K, p, e, W);
+    c.p = p32;
+    c.b0 = static_cast<float>(b0);
+    double ss = 1.0;
+    for (int k = 0; k < 3; ++k) {
+        ss /= e;
+        c.w[k] = static_cast<float>(W[k]);
+        c.ss[k] = static_cast<float>(ss);
+    }
+    c.lnp = std::log(p);
+    return c;
+}
+
+// Coloured Savitzky-Golay blur, Section 4.2.  Unknowns c_0..c_K with
+// h(0) = c_0, h(+-k) = c_k (unit-impulse pairs, Eq 16 with Delta_d = 0).
+// Minimise c^T S c (the coloured-noise gain, Eq 21) subject to F c = rho,
+// F rows: dc gain (c_0 + 2 sum c_k = 1) and zero second moment
+// (sum_k 2 k^2 c_k = 0), S = T Sbar T^T with
+//   Sbar(d) = (pi - omega_c)/pi (d = 0),  -sin(omega_c d)/(pi d) (d != 0).
+// Solved through the Schur complement: Y = S^-1 F^T (Cholesky), then
+// lambda = (F Y)^-1 rho and c = Y lambda, in long double.
+int colored_sg_taps(double sigma, int K, double omega_c, double *taps) {
+    (void)sigma;
+    typedef long double ld;
+    const int n = K + 1;
+    const ld pi = 3.141592653589793238462643383279502884L;
+    auto sbar = [&](int d) -> ld {
+        if (d == 0) return (pi - (ld)omega_c) / pi;
+        return -std::sin((ld)omega_c * (ld)d) / (pi * (ld)d);
+    };
+    std::vector<ld> S((size_t)n * n, 0.0L);
+    for (int k1 = 0; k1 < n; ++k1) {
+        for (int k2 = 0; k2 < n; ++k2) {
+            ld acc = 0.0L;
+            const int s1n = k1 == 0 ? 1 : 2, s2n = k2 == 0 ? 1 : 2;
+            for (int a = 0; a < s1n; ++a)
+                for (int b = 0; b < s2n; ++b) {
+                    const int m1 = a == 0 ? k1 : -k1;
+                    const int m2 = b == 0 ? k2 : -k2;
+                    acc += sbar(m1 - m2);
+                }
+            S[(size_t)k1 * n + k2] = acc;
+        }
+    }
+    // Cholesky S = L L^T (in place, lower triangle)
+    for (int j = 0; j < n; ++j) {
+        ld d = S[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) d -= S[(size_t)j * n + k] * S[(size_t)j * n + k];
+        if (!(d > 0.0L)) return -1;
+        d = std::sqrt(d);
+        S[(size_t)j * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            ld s = S[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) s -= S[(size_t)i * n + k] * S[(size_t)j * n + k];
+            S[(size_t)i * n + j] = s / d;
+        }
+    }
+    auto solve = [&](std::vector<ld> &v) {
+        for (int i = 0; i < n; ++i) {
+            ld s = v[i];
+            for (int k = 0; k < i; ++k) s -= S[(size_t)i * n + k] * v[k];
+            v[i] = s / S[(size_t)i * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            ld s = v[i];
+            for (int k = i + 1; k < n; ++k) s -= S[(size_t)k * n + i] * v[k];
+            v[i] = s / S[(size_t)i * n + i];
+        }
+    };
+    std::vector<ld> f0(n), f2(n);
+    for (int k = 0; k < n; ++k) {
+        f0[k] = k == 0 ? 1.0L : 2.0L;
+        f2[k] = 2.0L * (ld)k * (ld)k;
+    }
+    std::vector<ld> y0 = f0, y2 = f2;
+    solve(y0);
+    solve(y2);
+    ld m00 = 0, m01 = 0, m11 = 0;
+    for (int k = 0; k < n; ++k) {
+        m00 += f0[k] * y0[k];
+        m01 += f0[k] * y2[k];
+        m11 += f2[k] * y2[k];
+    }
+    const ld det = m00 * m11 - m01 * m01;
+    const ld l0 = m11 / det, l2 = -m01 / det;  // (F Y)^-1 [1, 0]^T
+    for (int m = -K; m <= K; ++m) {
+        const int k = m < 0 ? -m : m;
+        taps[m + K] = (double)(y0[k] * l0 + y2[k] * l2);
+    }
+    return 0;
+}
+
+// Sampled Gaussian (Eq 9c) on m = -K..K renormalised to unit dc gain (Eq 11).
+int gaussian_taps(double sigma, int K, double *taps) {
+    double sum = 0.0;
+    for (int m = -K; m <= K; ++m) {
+        taps[m + K] = std::exp(-(double)m * m / (2.0 * sigma * sigma));
+        sum += taps[m + K];
+    }
+    for (int m = -K; m <= K; ++m) taps[m + K] /= sum;
+    return 0;
+}
+
+}  // namespace fdvm

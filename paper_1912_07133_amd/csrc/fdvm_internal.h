@@ -1,0 +1,80 @@
+// Internal declarations shared by the C-ABI layer and the HIP kernels of the
+// blob-detection filter bank.  Not part of the public ABI (see include/fdvm.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fdvm.h"
+
+namespace fdvm {
+
+// ---------------------------------------------------------------- design
+// Repeated-pole blur (Section 4.3): DE coefficients at pole p (float64);
+// e = 1 - p is passed separately so it keeps full relative precision.
+void repeated_pole_de(int K, double p, double e, double *b0, double bp[4], double ap[4]);
+
+// Float32 realisation of the repeated-pole blur as a cascade of K first-order
+// sections sharing the pole p32 = fl32(p):
+//   v_1(n) = p32 v_1(n-1) + x(n),  v_k(n) = p32 v_k(n-1) + v_{k-1}(n),
+//   y+(n)  = sum_k w[k-1] v_k(n-1)          (causal part of Eq A10a)
+// and the mirror image for the anti-causal part; w and b0 are the float64
+// design at p32 rounded once.  ss[k-1] = 1/(1 - p32)^k is the steady-state
+// value of v_k for a unit constant input (Eq A32 read as replicate extension).
+struct Cascade {
+    float p;
+    float b0;
+    float w[3];
+    float ss[3];
+    double lnp;  // log(p32), for p32^n at run-time lengths
+};
+Cascade cascade_realisation(int K, double sigma);
+
+// Coloured Savitzky-Golay / Gaussian FIR designs (float64, h(-K..K)).
+int colored_sg_taps(double sigma, int K, double omega_c, double *taps);
+int gaussian_taps(double sigma, int K, double *taps);
+
+// ---------------------------------------------------------------- kernels
+constexpr int IIR_TILE = 32;  // samples per tile along the recursion
+
+struct IirScaleParams {
+    float p, b0;
+    float w[3];
+    float ss[3];
+    float p_tile;  // p^IIR_TILE
+    float pad;
+    double lnp;
+};
+
+struct IirParams {
+    int nscales;
+    int order;
+    int boundary;  // fdvm_boundary
+    int pad;
+    IirScaleParams s[FDVM_MAX_SCALES];
+};
+
+hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
+                           float *out, int64_t out_pitch, int64_t plane_stride,
+                           const IirParams &prm, hipStream_t stream);
+hipError_t launch_iir_cols(float *data, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                           const IirParams &prm, hipStream_t stream);
+
+hipError_t launch_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                           int nscales, const float *norms, unsigned what,
+                           float *out, int64_t out_plane_stride, hipStream_t stream);
+
+size_t detect_workspace_bytes(int64_t H, int64_t W, int nscales);
+hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                         int nscales, float tau, int border, fdvm_blob *out, int32_t cap,
+                         int32_t *count, void *ws, hipStream_t stream);
+
+bool fir_mfma_available();
+size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half);
+hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
+                      float *out, int64_t out_pitch, int64_t plane_stride,
+                      const double *taps, const int32_t *half_len, const int32_t *tap_offset,
+                      int nscales, int boundary, int algo, void *ws, size_t ws_bytes,
+                      hipStream_t stream);
+
+}  // namespace fdvm

@@ -1,0 +1,127 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, its host-only filter design matches the oracle, and the
+host-side argument validation rejects bad calls before touching a device."""
+
+import ctypes
+import math
+
+import numpy as np
+import pytest
+
+import paper_1912_07133_amd as P
+from oracle import design
+
+pytestmark = pytest.mark.skipif(not P.library_available(), reason="libfdvm.so not built")
+
+
+def test_every_header_symbol_is_exported():
+    syms = P.header_symbols()
+    assert set(syms) >= {"fdvm_filter_design", "fdvm_blur_iir", "fdvm_blur_fir", "fdvm_highpass",
+                         "fdvm_detect_blobs", "fdvm_workspace_bytes", "fdvm_status_string"}
+    L = P.lib()
+    for name in syms:
+        assert hasattr(L, name), name
+
+
+def test_struct_layouts_match_header():
+    assert ctypes.sizeof(P.Blob) == 20
+    assert ctypes.sizeof(P.Filter) == 8 + 8 * 3 + 8 * 4 * 2 + 8 * 2 + 8
+
+
+@pytest.mark.parametrize("sigma", [0.3, 1.0, 2.0, 8.0, 23.8, 64.0, 96.0, 1000.0])
+def test_iir_design_matches_table_iv(sigma):
+    d = P.filter_design("iir", sigma, order=3)
+    t = design.table_iv(sigma)
+    assert d["p"] == pytest.approx(math.exp(-1 / sigma), rel=1e-15)
+    assert d["b0"] == pytest.approx(t.b0, rel=1e-9, abs=1e-16)
+    for m in range(4):
+        assert d["bp"][m] == pytest.approx(t.bp[m], rel=1e-7 if sigma > 500 else 1e-10, abs=1e-16)
+        assert d["ap"][m] == pytest.approx(t.ap[m], rel=1e-14)
+    assert d["side_gain"] == pytest.approx((1 - t.b0) / 2, rel=1e-12)
+
+
+@pytest.mark.parametrize("sigma", [0.5, 1.5, 4.0, 12.0, 64.0])
+def test_iir_order2_design_matches_general_procedure(sigma):
+    d = P.filter_design("iir", sigma, order=2)
+    g = design.repeated_pole(2, sigma)
+    assert d["b0"] == pytest.approx(g.b0, rel=1e-10)
+    for m in range(3):
+        assert d["bp"][m] == pytest.approx(g.bp[m], rel=1e-9, abs=1e-16)
+        assert d["ap"][m] == pytest.approx(g.ap[m], rel=1e-14)
+
+
+@pytest.mark.parametrize("sigma", [2.0, 3.28, 8.83, 23.8, 64.0, 96.0])
+def test_colored_sg_taps_match_oracle(sigma):
+    got = P.filter_design("sg", sigma)["taps"]
+    ref = design.colored_sg_taps(sigma)
+    assert len(got) == len(ref) == 2 * math.ceil(3 * sigma - 1e-9) + 1
+    assert np.max(np.abs(got - ref)) <= 1e-9 * np.max(np.abs(ref))
+
+
+def test_fir_length_override_and_gaussian():
+    d = P.filter_design("sg", 10.0, fir_half_len=64)
+    assert d["ntaps"] == 129
+    # K = 6.4 sigma: S of Eq 22 has condition number ~2e15, so two float64
+    # solves agree only to ~1e-7 relative; both meet the constraints exactly
+    ref = design.colored_sg_taps(10.0, K=64)
+    assert np.max(np.abs(d["taps"] - ref)) < 1e-6 * np.max(np.abs(ref))
+    m = np.arange(-64, 65)
+    assert abs(d["taps"].sum() - 1) < 1e-14 and abs((m * m * d["taps"]).sum()) < 1e-9
+    g = P.filter_design("gaussian", 4.0, fir_half_len=20)["taps"]
+    assert np.max(np.abs(g - design.gaussian_taps(4.0, 20))) < 1e-15
+
+
+def test_design_errors():
+    L = P.lib()
+    f = P.Filter()
+    buf = (ctypes.c_double * 10)()
+    assert L.fdvm_filter_design(0, 3, 8.0, 0, None, None, 0) == P.EINVAL
+    assert L.fdvm_filter_design(0, 4, 8.0, 0, ctypes.byref(f), None, 0) == P.EINVAL
+    assert L.fdvm_filter_design(0, 3, 0.1, 0, ctypes.byref(f), None, 0) == P.ERANGE
+    assert L.fdvm_filter_design(0, 3, float("nan"), 0, ctypes.byref(f), None, 0) == P.ERANGE
+    assert L.fdvm_filter_design(1, 0, 8.0, 0, ctypes.byref(f), buf, 10) == P.ENOMEM
+    assert L.fdvm_filter_design(1, 0, 8.0, 0, ctypes.byref(f), None, 0) == P.EINVAL
+    assert L.fdvm_filter_design(1, 0, 8.0, 600, ctypes.byref(f), buf, 10) == P.ERANGE
+    assert L.fdvm_filter_design(7, 3, 8.0, 0, ctypes.byref(f), None, 0) == P.EINVAL
+    assert P.status_string(P.EOVERFLOW) == "detection list overflow"
+
+
+def test_device_calls_validate_on_the_host():
+    """Bad arguments are rejected before any HIP call (no GPU in this test)."""
+    L = P.lib()
+    f = P.Filter()
+    assert L.fdvm_filter_design(0, 3, 4.0, 0, ctypes.byref(f), None, 0) == P.OK
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    filt = (P.Filter * 1)(f)
+    assert L.fdvm_blur_iir(None, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 0, 8, 8, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 4, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 0, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 17, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, 9, 8, 8, 8, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 5, None) == P.EINVAL
+    two = (P.Filter * 2)(f, f)
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 10, two, 2, 0, None) == P.EINVAL  # stride
+    f2 = P.Filter()
+    assert L.fdvm_filter_design(0, 2, 4.0, 0, ctypes.byref(f2), None, 0) == P.OK
+    mixed = (P.Filter * 2)(f, f2)
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, mixed, 2, 0, None) == P.EINVAL
+    sig = (ctypes.c_double * 1)(2.0)
+    assert L.fdvm_highpass(fake, 8, 8, 8, 64, 1, sig, 0, 1, fake, 64, None) == P.EINVAL
+    assert L.fdvm_highpass(fake, 8, 8, 8, 64, 1, sig, 64, 1, fake, 64, None) == P.EINVAL
+    assert L.fdvm_highpass(fake, 8, 8, 8, 64, 1, sig, 3, 1, fake, 10, None) == P.EINVAL
+    assert L.fdvm_detect_blobs(fake, 8, 8, 8, 64, 1, -1.0, 1, fake, 10, fake, fake, 1 << 20, None) == P.EINVAL
+    assert L.fdvm_detect_blobs(fake, 8, 8, 8, 64, 1, 0.5, 1, fake, 10, fake, fake, 1, None) == P.ENOMEM
+    half = (ctypes.c_int32 * 1)(2)
+    off = (ctypes.c_int32 * 1)(0)
+    asym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.11)
+    assert L.fdvm_blur_fir(fake, P.F32, 8, 8, 8, fake, 8, 64, asym, half, off, 1, 0, 0, fake, 1 << 20,
+                           None) == P.EINVAL
+    sym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.1)
+    assert L.fdvm_blur_fir(fake, P.F32, 8, 8, 8, fake, 8, 64, sym, half, off, 1, 0, 0, fake, 4, None) == P.ENOMEM
+
+
+def test_workspace_sizes():
+    assert P.workspace_bytes(P.OP_BLUR_IIR, 2048, 2048, 8) == 0
+    assert P.workspace_bytes(P.OP_BLUR_FIR, 2048, 2048, 8, 192) >= 2048 * 2048 * 4
+    assert P.workspace_bytes(P.OP_DETECT, 2048, 2048, 8) >= 8 * 2048 * (2048 // 64) * 8
