@@ -124,7 +124,9 @@ const char *fdvm_status_string(fdvm_status status);
  *     H(pi) = 0).  sigma in [0.25, 4096].  `fir_half_len`, `taps`,
  *     `taps_cap` are ignored (taps may be NULL).
  *   kind = FDVM_FIR_COLORED_SG: Eq 20 solved in float64 with S from Eq 22,
- *     omega_c = 3/sigma and dc constraints rho = [1, 0] (D = 3);
+ *     omega_c = 3/sigma and dc constraints rho = [1, 0] (D = 3); needs
+ *     omega_c < pi (sigma > 3/pi), otherwise the stopband of Eq 21 is empty
+ *     and the call returns FDVM_ERANGE;
  *     kind = FDVM_FIR_GAUSSIAN: Eq 9c sampled on m = -K..K, normalised by Eq 11.
  *     Half-length K = fir_half_len if > 0, else ceil(3 sigma) (length
  *     6 sigma + 1).  K must be in [1, FDVM_MAX_FIR_HALF]; sigma in [0.25, 1024].
@@ -158,6 +160,25 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
 fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
                           float *out, int64_t out_pitch, int64_t plane_stride,
                           const fdvm_filter *filters, int nscales, fdvm_boundary bc,
+                          void *stream);
+
+/*
+ * fdvm_iir_pass -- one of the two 1-D passes that fdvm_blur_iir chains
+ * (Section 2: two sequential 1-D filtering operations, x then y).
+ *   axis = 0 (x, along rows): `in` is one frame of type dt (row pitch
+ *             in_pitch, in_plane_stride ignored); writes nscales float32
+ *             planes to `out` (as fdvm_blur_iir).  `in` and `out` must not
+ *             overlap.
+ *   axis = 1 (y, along columns): `in` holds nscales float32 planes (dt must be
+ *             FDVM_F32, pitch in_pitch, plane stride in_plane_stride); each
+ *             plane s is filtered with filters[s] into out plane s.  In-place
+ *             operation (in == out with equal pitch and stride) is allowed;
+ *             other overlaps are not.
+ * Errors as fdvm_blur_iir.
+ */
+fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                          int64_t in_plane_stride, float *out, int64_t out_pitch, int64_t plane_stride,
+                          const fdvm_filter *filters, int nscales, fdvm_boundary bc, int axis,
                           void *stream);
 
 /*

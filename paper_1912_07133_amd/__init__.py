@@ -83,6 +83,9 @@ def lib() -> ctypes.CDLL:
         L.fdvm_blur_iir.restype = ctypes.c_int
         L.fdvm_blur_iir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
                                     ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, vp]
+        L.fdvm_iir_pass.restype = ctypes.c_int
+        L.fdvm_iir_pass.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, vp, i64, i64,
+                                    ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
         L.fdvm_blur_fir.restype = ctypes.c_int
         L.fdvm_blur_fir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
                                     ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -192,6 +195,41 @@ def blur_iir(x, sigmas: Sequence[float], order: int = 3, boundary: str = "replic
     return out
 
 
+def iir_designs(sigmas: Sequence[float], order: int = 3):
+    """ctypes array of fdvm_filter designs, one per scale (fdvm_filter_design)."""
+    filt = (Filter * len(sigmas))()
+    for i, s in enumerate(sigmas):
+        _check(lib().fdvm_filter_design(IIR_REPEATED_POLE, order, float(s), 0, ctypes.byref(filt[i]), None, 0),
+               "fdvm_filter_design")
+    return filt
+
+
+def iir_pass(x, sigmas: Sequence[float], axis: int, order: int = 3, boundary: str = "replicate", out=None):
+    """One 1-D pass of the IIR blur (fdvm_iir_pass).  axis 0: frame [H, W] ->
+    [S, H, W] filtered along x; axis 1: planes [S, H, W] (float32) filtered
+    along y (out may be the input itself)."""
+    torch = _torch()
+    S = len(sigmas)
+    filt = iir_designs(sigmas, order)
+    if axis == 0:
+        x = _frame(x)
+        H, W = x.shape
+        in_plane = 0
+        dt = _dtype_code(x)
+        pitch = x.stride(0)
+    else:
+        if x.dtype != torch.float32 or x.dim() != 3 or x.stride(2) != 1:
+            raise ValueError("axis 1 needs float32 planes [S, H, W] with unit x stride")
+        _, H, W = x.shape
+        in_plane, pitch, dt = x.stride(0), x.stride(1), F32
+    if out is None:
+        out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    _check(lib().fdvm_iir_pass(x.data_ptr(), dt, H, W, pitch, in_plane, out.data_ptr(), out.stride(1),
+                               out.stride(0), filt, S, BOUNDARIES[boundary], axis, _stream_ptr(x.device)),
+           "fdvm_iir_pass")
+    return out
+
+
 def fir_taps(kind: str, sigmas: Sequence[float], half_lens: Sequence[int] | None = None):
     """Designs for fdvm_blur_fir: (taps float64 concatenated, half_len, offsets)."""
     taps, half, off = [], [], []
@@ -296,6 +334,6 @@ def scale_of(sigma: float) -> float:
     return 2.0 * sigma
 
 
-__all__ = ["filter_design", "blur_iir", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
+__all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
            "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of"]
 _ = math

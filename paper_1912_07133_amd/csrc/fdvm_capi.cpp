@@ -83,6 +83,7 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
         int rc;
         if (kind == FDVM_FIR_COLORED_SG) {
             f.omega_c = 3.0 / sigma;
+            if (!(f.omega_c < 3.141592653589793)) return FDVM_ERANGE;
             rc = colored_sg_taps(sigma, K, f.omega_c, taps);
         } else {
             rc = gaussian_taps(sigma, K, taps);
@@ -105,30 +106,22 @@ size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_h
     }
 }
 
-fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
-                          int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
-                          fdvm_boundary bc, void *stream) {
-    fdvm_status st = check_image(in, H, W, in_pitch);
-    if (st != FDVM_OK) return st;
-    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
-    if (st != FDVM_OK) return st;
+namespace {
+fdvm_status iir_params(const fdvm_filter *filters, int nscales, fdvm_boundary bc, IirParams *prm) {
     if (!filters) return FDVM_EINVAL;
-    if (dt != FDVM_U16 && dt != FDVM_F32 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
     if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
-    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
     const int order = filters[0].order;
     if (order != 2 && order != 3) return FDVM_EINVAL;
-    IirParams prm;
-    std::memset(&prm, 0, sizeof(prm));
-    prm.nscales = nscales;
-    prm.order = order;
-    prm.boundary = bc;
+    std::memset(prm, 0, sizeof(*prm));
+    prm->nscales = nscales;
+    prm->order = order;
+    prm->boundary = bc;
     for (int s = 0; s < nscales; ++s) {
         const fdvm_filter &f = filters[s];
         if (f.kind != FDVM_IIR_REPEATED_POLE || f.order != order) return FDVM_EINVAL;
         if (!(f.sigma >= 0.25 && f.sigma <= 4096.0)) return FDVM_ERANGE;
         const Cascade c = cascade_realisation(order, f.sigma);
-        IirScaleParams &q = prm.s[s];
+        IirScaleParams &q = prm->s[s];
         q.p = c.p;
         q.b0 = c.b0;
         for (int k = 0; k < 3; ++k) {
@@ -138,11 +131,46 @@ fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
         q.lnp = c.lnp;
         q.p_tile = (float)std::exp(IIR_TILE * c.lnp);
     }
+    return FDVM_OK;
+}
+}  // namespace
+
+fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                          int64_t in_plane_stride, float *out, int64_t out_pitch, int64_t plane_stride,
+                          const fdvm_filter *filters, int nscales, fdvm_boundary bc, int axis, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (dt != FDVM_U16 && dt != FDVM_F32 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
+    IirParams prm;
+    st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs);
-    if (e != hipSuccess) return FDVM_EDEVICE;
-    e = launch_iir_cols(out, H, W, out_pitch, plane_stride, prm, hs);
-    return from_hip(e);
+    if (axis == 0) {
+        if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+        return from_hip(launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs));
+    }
+    if (axis == 1) {
+        if (dt != FDVM_F32) return FDVM_EINVAL;
+        if (nscales > 1 && in_plane_stride < H * in_pitch) return FDVM_EINVAL;
+        const bool same = in == static_cast<const void *>(out);
+        if (same && (in_pitch != out_pitch || (nscales > 1 && in_plane_stride != plane_stride)))
+            return FDVM_EINVAL;
+        return from_hip(launch_iir_cols(static_cast<const float *>(in), in_pitch, in_plane_stride, out, H, W,
+                                        out_pitch, plane_stride, prm, hs));
+    }
+    return FDVM_EINVAL;
+}
+
+fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                          int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
+                          fdvm_boundary bc, void *stream) {
+    fdvm_status st = fdvm_iir_pass(in, dt, H, W, in_pitch, 0, out, out_pitch, plane_stride, filters, nscales, bc,
+                                   0, stream);
+    if (st != FDVM_OK) return st;
+    return fdvm_iir_pass(out, FDVM_F32, H, W, out_pitch, plane_stride, out, out_pitch, plane_stride, filters,
+                         nscales, bc, 1, stream);
 }
 
 fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,

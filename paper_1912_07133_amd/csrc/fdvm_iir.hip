@@ -326,7 +326,8 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 // ------------------------------------------------------------ column pass
 template <int K>
 __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
-    float *__restrict__ data, int64_t pitch, int64_t plane_stride, int H, int W, int seg, Args a) {
+    const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out, int64_t pitch,
+    int64_t plane_stride, int H, int W, int seg, Args a) {
     constexpr int TW = COL_TW;
     extern __shared__ float tst[];            // [COL_NW][ntmax][K][64]
     __shared__ float xz[COL_NW][2][K][64];
@@ -340,7 +341,8 @@ __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
     const ScaleArgs &cf = a.s[s];
     const float p = cf.p;
     const int ntmax = seg / TW;
-    float *plane = data + (int64_t)s * plane_stride;
+    const float *plane = in + (int64_t)s * in_plane_stride;   // read with in_pitch
+    float *oplane = out + (int64_t)s * plane_stride;          // written with pitch
 
     const int r0 = wv * seg;
     const int r1 = min(r0 + seg, H);
@@ -357,7 +359,7 @@ __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
         float xs[TW];
 #pragma unroll
         for (int j = 0; j < TW; ++j)
-            xs[j] = (j < lt) ? plane[(int64_t)(rt + j) * pitch + ccol] : 0.0f;
+            xs[j] = (j < lt) ? plane[(int64_t)(rt + j) * in_pitch + ccol] : 0.0f;
 #pragma unroll
         for (int j = 0; j < TW; ++j) cas_step(p, zf, xs[j]);
         float u[K];
@@ -386,7 +388,7 @@ __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
 
     // ---- carries entering this segment from above (forward) and below
     const float x_top = plane[ccol];
-    const float x_bot = plane[(int64_t)(H - 1) * pitch + ccol];
+    const float x_bot = plane[(int64_t)(H - 1) * in_pitch + ccol];
     float cfw[K], cbw[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
         for (int k = 0; k < K; ++k) vb[k] = my[(t * K + k) * 64 + lane];
         if (lt == TW) {
 #pragma unroll
-            for (int j = 0; j < TW; ++j) xs[j] = plane[(int64_t)(rt + j) * pitch + ccol];
+            for (int j = 0; j < TW; ++j) xs[j] = plane[(int64_t)(rt + j) * in_pitch + ccol];
 #pragma unroll
             for (int j = TW - 1; j >= 0; --j) {
                 ys[j] = fmaf(cf.b0, xs[j], cas_out(cf, vb));
@@ -463,12 +465,12 @@ __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
             }
             if (col_ok) {
 #pragma unroll
-                for (int j = 0; j < TW; ++j) plane[(int64_t)(rt + j) * pitch + col] = ys[j];
+                for (int j = 0; j < TW; ++j) oplane[(int64_t)(rt + j) * pitch + col] = ys[j];
             }
         } else {
 #pragma unroll
             for (int j = 0; j < TW; ++j)
-                xs[j] = (j < lt) ? plane[(int64_t)(rt + j) * pitch + ccol] : 0.0f;
+                xs[j] = (j < lt) ? plane[(int64_t)(rt + j) * in_pitch + ccol] : 0.0f;
 #pragma unroll
             for (int j = TW - 1; j >= 0; --j) {
                 if (j < lt) {
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
             if (col_ok) {
 #pragma unroll
                 for (int j = 0; j < TW; ++j)
-                    if (j < lt) plane[(int64_t)(rt + j) * pitch + col] = ys[j];
+                    if (j < lt) oplane[(int64_t)(rt + j) * pitch + col] = ys[j];
             }
         }
     }
@@ -566,7 +568,8 @@ size_t iir_cols_lds_bytes(int64_t H, int order, int *seg_out) {
     return (size_t)COL_NW * (seg / COL_TW) * order * 64 * sizeof(float);
 }
 
-hipError_t launch_iir_cols(float *data, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
+                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                            const IirParams &prm, hipStream_t st) {
     int seg = 0;
     const size_t lds = iir_cols_lds_bytes(H, prm.order, &seg);
@@ -574,11 +577,11 @@ hipError_t launch_iir_cols(float *data, int64_t H, int64_t W, int64_t pitch, int
     Args a = make_args(prm, 1, seg);
     dim3 grid((unsigned)((W + 63) / 64), (unsigned)prm.nscales);
     if (prm.order == 3) {
-        hipLaunchKernelGGL((iir_cols_kernel<3>), grid, dim3(COL_NW * 64), lds, st, data, pitch,
-                           plane_stride, (int)H, (int)W, seg, a);
+        hipLaunchKernelGGL((iir_cols_kernel<3>), grid, dim3(COL_NW * 64), lds, st, in, in_pitch,
+                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, seg, a);
     } else if (prm.order == 2) {
-        hipLaunchKernelGGL((iir_cols_kernel<2>), grid, dim3(COL_NW * 64), lds, st, data, pitch,
-                           plane_stride, (int)H, (int)W, seg, a);
+        hipLaunchKernelGGL((iir_cols_kernel<2>), grid, dim3(COL_NW * 64), lds, st, in, in_pitch,
+                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, seg, a);
     } else {
         return hipErrorInvalidValue;
     }

@@ -57,7 +57,8 @@ struct IirParams {
 hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
                            float *out, int64_t out_pitch, int64_t plane_stride,
                            const IirParams &prm, hipStream_t stream);
-hipError_t launch_iir_cols(float *data, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
+                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                            const IirParams &prm, hipStream_t stream);
 
 hipError_t launch_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
