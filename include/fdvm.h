@@ -142,7 +142,7 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
  * fdvm_blur_iir -- separable repeated-pole IIR blur of one frame at nscales
  * scales (Eqs A6-A10, x then y; Sections 2 and 5).
  *   in        device, H x W elements of type dt, row pitch in_pitch (>= W)
- *             (u16 and f32/f16/bf16 are converted to float on load; u16 is
+ *             (u16, f16, bf16 and f32 are converted to float on load; u16 is
  *             exact for the 12-bit frames this is built for)
  *   out       device float32, nscales planes; plane s, pixel (y, x) at
  *             out[s * plane_stride + y * out_pitch + x]; out_pitch >= W,
@@ -150,17 +150,20 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
  *   filters   host array of nscales IIR designs (fdvm_filter_design output);
  *             each must be FDVM_IIR_REPEATED_POLE with the same order (2 or 3).
  *   bc        boundary extension (see conventions).
- *   The recursions run in float32 as a cascade of K first-order sections with
- *   the pole rounded once to float32 and the output weights designed in
- *   float64 for that rounded pole.
- * Returns FDVM_EINVAL on bad arguments (H, W < 1, nscales outside
+ *   ws        device workspace of at least
+ *             fdvm_workspace_bytes(FDVM_OP_BLUR_IIR, H, W, nscales, 0) bytes
+ *             (the chunk states of the column pass); contents on entry do not
+ *             matter.
+ *   The recursions run as a cascade of K first-order sections with float64
+ *   states and weights; the planes are stored as float32.
+ * Returns FDVM_EINVAL on bad arguments (H, W out of range, nscales outside
  * [1, FDVM_MAX_SCALES], mixed orders, pitch/stride too small, null pointers),
- * FDVM_EDEVICE if a launch fails.
+ * FDVM_ENOMEM (workspace too small), FDVM_EDEVICE if a launch fails.
  */
 fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
                           float *out, int64_t out_pitch, int64_t plane_stride,
                           const fdvm_filter *filters, int nscales, fdvm_boundary bc,
-                          void *stream);
+                          void *ws, size_t ws_bytes, void *stream);
 
 /*
  * fdvm_iir_pass -- one of the two 1-D passes that fdvm_blur_iir chains
@@ -168,18 +171,37 @@ fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
  *   axis = 0 (x, along rows): `in` is one frame of type dt (row pitch
  *             in_pitch, in_plane_stride ignored); writes nscales float32
  *             planes to `out` (as fdvm_blur_iir).  `in` and `out` must not
- *             overlap.
+ *             overlap.  ws may be NULL.
  *   axis = 1 (y, along columns): `in` holds nscales float32 planes (dt must be
  *             FDVM_F32, pitch in_pitch, plane stride in_plane_stride); each
  *             plane s is filtered with filters[s] into out plane s.  In-place
  *             operation (in == out with equal pitch and stride) is allowed;
- *             other overlaps are not.
+ *             other overlaps are not.  ws as for fdvm_blur_iir.
+ *   axis = 2 (y, then the high-pass stage): as axis = 1, but out plane s
+ *             receives sigma_s^2 (D20 + D02) of the blurred plane (see
+ *             fdvm_iir_laplacian); `in` and `out` must not overlap.
  * Errors as fdvm_blur_iir.
  */
 fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
                           int64_t in_plane_stride, float *out, int64_t out_pitch, int64_t plane_stride,
                           const fdvm_filter *filters, int nscales, fdvm_boundary bc, int axis,
-                          void *stream);
+                          void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * fdvm_iir_laplacian -- the IIR blur and the high-pass stage in one call:
+ * writes V_s = sigma_s^2 (D20 + D02) of the repeated-pole blur B_s (Table I
+ * d = 2 taps along x and along y, clamp-to-edge extension of B_s), i.e. what
+ * fdvm_blur_iir followed by fdvm_highpass(FDVM_HP_LAPLACIAN, normalize = 1)
+ * computes, without storing B_s: the Laplacian is formed in float64 from the
+ * unrounded blur.
+ *   Arguments as fdvm_blur_iir; `out` receives the V planes; ws of at least
+ *   fdvm_workspace_bytes(FDVM_OP_IIR_LAPLACIAN, H, W, nscales, 0) bytes (holds
+ *   the x-pass planes and the column-pass states).
+ */
+fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                               float *out, int64_t out_pitch, int64_t plane_stride,
+                               const fdvm_filter *filters, int nscales, fdvm_boundary bc,
+                               void *ws, size_t ws_bytes, void *stream);
 
 /*
  * fdvm_blur_fir -- separable FIR blur (Eq A5), x then y, nscales scales.
@@ -205,7 +227,7 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
                           void *ws, size_t ws_bytes, void *stream);
 
 /* workspace sizes */
-enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2 };
+enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3 };
 
 /* Bytes of device workspace `op` needs for an H x W frame with nscales
  * scales and maximum FIR half-length max_half_len (0 if unused). */

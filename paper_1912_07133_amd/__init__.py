@@ -29,7 +29,7 @@ BC_REPLICATE, BC_ZERO = 0, 1
 U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
-OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT = 0, 1, 2
+OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN = 0, 1, 2, 3
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
 
@@ -82,10 +82,14 @@ def lib() -> ctypes.CDLL:
         L.fdvm_workspace_bytes.argtypes = [ctypes.c_int, i64, i64, ctypes.c_int, ctypes.c_int]
         L.fdvm_blur_iir.restype = ctypes.c_int
         L.fdvm_blur_iir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
-                                    ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, vp]
+                                    ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
+        L.fdvm_iir_laplacian.restype = ctypes.c_int
+        L.fdvm_iir_laplacian.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
+                                         ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
         L.fdvm_iir_pass.restype = ctypes.c_int
         L.fdvm_iir_pass.argtypes = [vp, ctypes.c_int, i64, i64, i64, i64, vp, i64, i64,
-                                    ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp]
+                                    ctypes.POINTER(Filter), ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                    ctypes.c_size_t, vp]
         L.fdvm_blur_fir.restype = ctypes.c_int
         L.fdvm_blur_fir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
                                     ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32),
@@ -177,21 +181,45 @@ def _frame(x):
     return x
 
 
-def blur_iir(x, sigmas: Sequence[float], order: int = 3, boundary: str = "replicate", out=None):
+def _workspace(op, H, W, S, device, workspace=None, max_half=0):
+    torch = _torch()
+    need = workspace_bytes(op, H, W, S, max_half)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+    return workspace
+
+
+def blur_iir(x, sigmas: Sequence[float], order: int = 3, boundary: str = "replicate", out=None, workspace=None):
     """Repeated-pole IIR blur (fdvm_blur_iir): [H, W] -> float32 [S, H, W]."""
     torch = _torch()
     x = _frame(x)
     H, W = x.shape
     S = len(sigmas)
-    filt = (Filter * S)()
-    for i, s in enumerate(sigmas):
-        _check(lib().fdvm_filter_design(IIR_REPEATED_POLE, order, float(s), 0, ctypes.byref(filt[i]), None, 0),
-               "fdvm_filter_design")
+    filt = iir_designs(sigmas, order)
     if out is None:
         out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    ws = _workspace(OP_BLUR_IIR, H, W, S, x.device, workspace)
     _check(lib().fdvm_blur_iir(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(), out.stride(1),
-                               out.stride(0), filt, S, BOUNDARIES[boundary], _stream_ptr(x.device)),
-           "fdvm_blur_iir")
+                               out.stride(0), filt, S, BOUNDARIES[boundary], ws.data_ptr(), ws.numel(),
+                               _stream_ptr(x.device)), "fdvm_blur_iir")
+    return out
+
+
+def iir_laplacian(x, sigmas: Sequence[float], order: int = 3, boundary: str = "replicate", out=None,
+                  workspace=None):
+    """Blur + normalised Laplacian in one call (fdvm_iir_laplacian):
+    [H, W] -> float32 V [S, H, W]."""
+    torch = _torch()
+    x = _frame(x)
+    H, W = x.shape
+    S = len(sigmas)
+    filt = iir_designs(sigmas, order)
+    if out is None:
+        out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    ws = _workspace(OP_IIR_LAPLACIAN, H, W, S, x.device, workspace)
+    _check(lib().fdvm_iir_laplacian(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(),
+                                    out.stride(1), out.stride(0), filt, S, BOUNDARIES[boundary], ws.data_ptr(),
+                                    ws.numel(), _stream_ptr(x.device)), "fdvm_iir_laplacian")
     return out
 
 
@@ -204,10 +232,12 @@ def iir_designs(sigmas: Sequence[float], order: int = 3):
     return filt
 
 
-def iir_pass(x, sigmas: Sequence[float], axis: int, order: int = 3, boundary: str = "replicate", out=None):
-    """One 1-D pass of the IIR blur (fdvm_iir_pass).  axis 0: frame [H, W] ->
+def iir_pass(x, sigmas: Sequence[float], axis: int, order: int = 3, boundary: str = "replicate", out=None,
+             workspace=None):
+    """One pass of the IIR blur (fdvm_iir_pass).  axis 0: frame [H, W] ->
     [S, H, W] filtered along x; axis 1: planes [S, H, W] (float32) filtered
-    along y (out may be the input itself)."""
+    along y (out may be the input itself); axis 2: as 1, then the normalised
+    Laplacian."""
     torch = _torch()
     S = len(sigmas)
     filt = iir_designs(sigmas, order)
@@ -219,14 +249,15 @@ def iir_pass(x, sigmas: Sequence[float], axis: int, order: int = 3, boundary: st
         pitch = x.stride(0)
     else:
         if x.dtype != torch.float32 or x.dim() != 3 or x.stride(2) != 1:
-            raise ValueError("axis 1 needs float32 planes [S, H, W] with unit x stride")
+            raise ValueError("axes 1, 2 need float32 planes [S, H, W] with unit x stride")
         _, H, W = x.shape
         in_plane, pitch, dt = x.stride(0), x.stride(1), F32
     if out is None:
         out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    ws = _workspace(OP_BLUR_IIR, H, W, S, x.device, workspace)
     _check(lib().fdvm_iir_pass(x.data_ptr(), dt, H, W, pitch, in_plane, out.data_ptr(), out.stride(1),
-                               out.stride(0), filt, S, BOUNDARIES[boundary], axis, _stream_ptr(x.device)),
-           "fdvm_iir_pass")
+                               out.stride(0), filt, S, BOUNDARIES[boundary], axis, ws.data_ptr(), ws.numel(),
+                               _stream_ptr(x.device)), "fdvm_iir_pass")
     return out
 
 
@@ -322,10 +353,10 @@ def detect(frame, sigmas: Sequence[float], tau: float, kind: str = "iir", order:
     """The whole filter bank: blur (IIR or FIR) -> normalised Laplacian ->
     multi-scale extrema.  Returns (blob list, Laplacian planes)."""
     if kind == "iir":
-        B = blur_iir(frame, sigmas, order=order, boundary=boundary)
+        V = iir_laplacian(frame, sigmas, order=order, boundary=boundary)
     else:
         B = blur_fir(frame, sigmas, kind=kind, boundary=boundary, algo=algo)
-    V = highpass(B, sigmas, HP_LAPLACIAN, True)
+        V = highpass(B, sigmas, HP_LAPLACIAN, True)
     return detect_blobs(V, tau, border, cap), V
 
 
@@ -334,6 +365,6 @@ def scale_of(sigma: float) -> float:
     return 2.0 * sigma
 
 
-__all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
+__all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "iir_laplacian", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
            "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of"]
 _ = math

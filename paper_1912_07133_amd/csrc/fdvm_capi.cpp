@@ -99,7 +99,10 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
 size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len) {
     if (H < 1 || W < 1 || nscales < 1) return 0;
     switch (op) {
-        case FDVM_OP_BLUR_IIR: return 0;
+        case FDVM_OP_BLUR_IIR: return iir_cols_workspace_bytes(H, W, nscales, 3);
+        case FDVM_OP_IIR_LAPLACIAN:
+            return (((size_t)H * W * sizeof(float) + 255) & ~(size_t)255) * nscales +
+                   iir_cols_workspace_bytes(H, W, nscales, 3);
         case FDVM_OP_BLUR_FIR: return fir_workspace_bytes(H, W, nscales, max_half_len);
         case FDVM_OP_DETECT: return detect_workspace_bytes(H, W, nscales);
         default: return 0;
@@ -129,20 +132,25 @@ fdvm_status iir_params(const fdvm_filter *filters, int nscales, fdvm_boundary bc
             q.ss[k] = c.ss[k];
         }
         q.lnp = c.lnp;
-        q.p_tile = (float)std::exp(IIR_TILE * c.lnp);
+        q.sig2 = f.sigma * f.sigma;
     }
     return FDVM_OK;
+}
+
+fdvm_status check_dtype(fdvm_dtype dt) {
+    return (dt == FDVM_U16 || dt == FDVM_F32 || dt == FDVM_F16 || dt == FDVM_BF16) ? FDVM_OK : FDVM_EINVAL;
 }
 }  // namespace
 
 fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
                           int64_t in_plane_stride, float *out, int64_t out_pitch, int64_t plane_stride,
-                          const fdvm_filter *filters, int nscales, fdvm_boundary bc, int axis, void *stream) {
+                          const fdvm_filter *filters, int nscales, fdvm_boundary bc, int axis, void *ws,
+                          size_t ws_bytes, void *stream) {
     fdvm_status st = check_image(in, H, W, in_pitch);
     if (st != FDVM_OK) return st;
     st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
     if (st != FDVM_OK) return st;
-    if (dt != FDVM_U16 && dt != FDVM_F32 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
+    if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
     IirParams prm;
     st = iir_params(filters, nscales, bc, &prm);
     if (st != FDVM_OK) return st;
@@ -151,26 +159,65 @@ fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
         if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
         return from_hip(launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs));
     }
-    if (axis == 1) {
+    if (axis == 1 || axis == 2) {
         if (dt != FDVM_F32) return FDVM_EINVAL;
         if (nscales > 1 && in_plane_stride < H * in_pitch) return FDVM_EINVAL;
         const bool same = in == static_cast<const void *>(out);
-        if (same && (in_pitch != out_pitch || (nscales > 1 && in_plane_stride != plane_stride)))
+        if (same && (axis == 2 || in_pitch != out_pitch || (nscales > 1 && in_plane_stride != plane_stride)))
             return FDVM_EINVAL;
+        if (!ws) return FDVM_EINVAL;
+        if (ws_bytes < iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;
         return from_hip(launch_iir_cols(static_cast<const float *>(in), in_pitch, in_plane_stride, out, H, W,
-                                        out_pitch, plane_stride, prm, hs));
+                                        out_pitch, plane_stride, axis == 2, prm, ws, hs));
     }
     return FDVM_EINVAL;
 }
 
 fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
                           int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
-                          fdvm_boundary bc, void *stream) {
-    fdvm_status st = fdvm_iir_pass(in, dt, H, W, in_pitch, 0, out, out_pitch, plane_stride, filters, nscales, bc,
-                                   0, stream);
+                          fdvm_boundary bc, void *ws, size_t ws_bytes, void *stream) {
+    // validate everything (both passes) before enqueueing anything
+    fdvm_status st = check_image(in, H, W, in_pitch);
     if (st != FDVM_OK) return st;
-    return fdvm_iir_pass(out, FDVM_F32, H, W, out_pitch, plane_stride, out, out_pitch, plane_stride, filters,
-                         nscales, bc, 1, stream);
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
+    IirParams prm;
+    st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
+    if (!ws) return FDVM_EINVAL;
+    if (ws_bytes < iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;
+    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs);
+    if (e != hipSuccess) return FDVM_EDEVICE;
+    return from_hip(launch_iir_cols(out, out_pitch, plane_stride, out, H, W, out_pitch, plane_stride, false, prm,
+                                    ws, hs));
+}
+
+fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                               int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
+                               fdvm_boundary bc, void *ws, size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
+    IirParams prm;
+    st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
+    if (!ws) return FDVM_EINVAL;
+    const size_t plane_bytes = ((size_t)H * W * sizeof(float) + 255) & ~(size_t)255;
+    const size_t need = plane_bytes * nscales + iir_cols_workspace_bytes(H, W, nscales, prm.order);
+    if (ws_bytes < need) return FDVM_ENOMEM;
+    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    float *rows = static_cast<float *>(ws);                       // x-pass planes, pitch W
+    const int64_t rstride = (int64_t)(plane_bytes / sizeof(float));
+    void *states = static_cast<char *>(ws) + plane_bytes * nscales;
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, rows, W, rstride, prm, hs);
+    if (e != hipSuccess) return FDVM_EDEVICE;
+    return from_hip(launch_iir_cols(rows, W, rstride, out, H, W, out_pitch, plane_stride, true, prm, states, hs));
 }
 
 fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,

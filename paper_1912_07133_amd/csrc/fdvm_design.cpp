@@ -4,7 +4,7 @@
 //    constrained design with a single Nyquist constraint (K = 2).  The Table IV
 //    polynomials are evaluated in factored form in terms of p and e = 1 - p so
 //    that nothing cancels as p -> 1 (coarse scales).
-//  * Float32 cascade realisation of the same transfer function.
+//  * Cascade realisation (float64) of the same transfer function.
 //  * Coloured Savitzky-Golay FIR (Section 4.2, Eqs 20-22) and sampled Gaussian
 //    FIR (Eqs 9c, 11).
 #include <cmath>
@@ -80,21 +80,20 @@ void repeated_pole_de(int K, double p, double e, double *b0, double bp[4], doubl
 
 Cascade cascade_realisation(int K, double sigma) {
     Cascade c{};
-    const float p32 = static_cast<float>(std::exp(-1.0 / sigma));
-    const double p = static_cast<double>(p32);
-    const double e = 1.0 - p;  // exact: p32 and 1 are both doubles
+    const double p = std::exp(-1.0 / sigma);
+    const double e = -std::expm1(-1.0 / sigma);  // 1 - p to full relative precision
     double b0, bp[4], ap[4], W[3];
     de_coefficients(K, p, e, &b0, bp, ap);
     cascade_weights(K, p, e, W);
-    c.p = p32;
-    c.b0 = static_cast<float>(b0);
+    c.p = p;
+    c.b0 = b0;
     double ss = 1.0;
     for (int k = 0; k < 3; ++k) {
         ss /= e;
-        c.w[k] = static_cast<float>(W[k]);
-        c.ss[k] = static_cast<float>(ss);
+        c.w[k] = W[k];
+        c.ss[k] = ss;
     }
-    c.lnp = std::log(p);
+    c.lnp = -1.0 / sigma;
     return c;
 }
 

@@ -3,26 +3,39 @@
 // start.
 //
 // Realisation.  Each one-sided part is a cascade of K first-order sections
-// with the common pole p (float32):
+// with the common pole p:
 //     v_1(n) = p v_1(n-1) + x(n),   v_k(n) = p v_k(n-1) + v_{k-1}(n),
 //     y+(n)  = sum_k w_k v_k(n-1)
-// (2K flops per sample and direction).  The zero-input transition over n
-// samples is A^n = p^n [[1,0,0],[n,1,0],[n(n+1)/2,n,1]] (K = 3; the upper-left
-// 2x2 block for K = 2), which is what lets a line be cut into chunks that are
-// filtered independently from a zero state and then stitched together:
+// (2K multiply-adds per sample and direction).  The states and weights are
+// float64: on CDNA3/CDNA4 a float64 FMA issues at the same rate as a
+// (non-packed) float32 FMA, and float64 states keep the blur at the float32
+// rounding floor even where the poles crowd z = 1, which the scale-normalised
+// Laplacian (gain ~8 sigma^2) would otherwise amplify.  Planes are stored as
+// float32.
+//
+// The zero-input transition over n samples is
+//     A^n = p^n [[1,0,0],[n,1,0],[n(n+1)/2,n,1]]
+// (K = 3; the upper-left block for K = 2), so a line cut into chunks is the
+// chunks filtered from a zero state and stitched with
 //     state_after(chunk) = A^len state_before + zero_state_end(chunk).
 //
 // Row pass (x): one wavefront per image row (R wavefronts for wide rows).  The
 // row is staged through LDS with coalesced loads, each lane owns C consecutive
-// samples, the per-lane chunk states are combined with a log-step scan across
-// lanes (and across the R wavefronts through LDS), and the outputs go back
-// through LDS to coalesced stores.  All S scales are computed from one staged
-// copy of the row.
+// samples, the chunk states are combined by a log-step scan across lanes (and
+// across the R wavefronts through LDS), outputs go back through LDS to
+// coalesced stores.  All S scales are computed from one staged copy of the row.
 //
-// Column pass (y): lane = column (coalesced along the row), the 8 wavefronts
-// of a work-group split the column height into segments, each segment is
-// walked in tiles of 64 rows held in registers; segment carries are exchanged
-// in LDS.
+// Column pass (y), lane = column (coalesced along the row), 64-row tiles:
+//   states  -- every tile's zero-state end states (forward and backward);
+//   scan    -- per column, the states are chained into the true carries that
+//              enter every tile (forward from the top, backward from the bottom);
+//   final   -- every tile independently: backward sweep from its bottom carry,
+//              forward sweep from its top carry, output.  Optionally the
+//              scale-normalised Laplacian sigma^2 (D20 + D02) is formed here in
+//              float64 from the unrounded blur: y-neighbours come from the
+//              sweep itself (the rows just outside the tile are recovered by
+//              inverting one step of the recursion), x-neighbours from the
+//              adjacent lanes (tiles overlap by one column on each side).
 #include <cmath>
 
 #include "fdvm_internal.h"
@@ -31,17 +44,15 @@ namespace fdvm {
 namespace {
 
 constexpr int ROW_WPB = 8;   // wavefronts per row-pass work-group
-constexpr int COL_NW = 8;    // wavefronts per column-pass work-group
-constexpr int COL_TW = 64;   // rows per register tile in the column pass
+constexpr int CT = 64;       // rows per column tile
+constexpr int COL_WPB = 4;   // wavefronts (tiles) per column work-group
 
 struct ScaleArgs {
-    float p, b0;
-    float w[3];
-    float ss[3];
-    float pbit[7];    // p^(2^k), k = 0..6
-    float pchunk[8];  // row pass: p^(C 2^k), k = 0..7
-    float pseg;       // column pass: p^seg
-    float pad;
+    double p, inv_p, b0, sig2;
+    double w[3];
+    double ss[3];
+    double pbit[7];    // p^(2^k), k = 0..6
+    double pchunk[7];  // row pass: p^(C 2^k), k = 0..6
 };
 
 struct Args {
@@ -53,52 +64,60 @@ struct Args {
 
 // ------------------------------------------------------------ recursion
 template <int K>
-__device__ __forceinline__ float cas_out(const ScaleArgs &c, const float (&v)[K]) {
-    float y = c.w[0] * v[0];
+__device__ __forceinline__ double cas_out(const ScaleArgs &c, const double (&v)[K]) {
+    double y = c.w[0] * v[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) y = fmaf(c.w[k], v[k], y);
+    for (int k = 1; k < K; ++k) y = fma(c.w[k], v[k], y);
     return y;
 }
 
 template <int K>
-__device__ __forceinline__ void cas_step(float p, float (&v)[K], float x) {
-    v[0] = fmaf(p, v[0], x);
+__device__ __forceinline__ void cas_step(double p, double (&v)[K], double x) {
+    v[0] = fma(p, v[0], x);
 #pragma unroll
-    for (int k = 1; k < K; ++k) v[k] = fmaf(p, v[k], v[k - 1]);
+    for (int k = 1; k < K; ++k) v[k] = fma(p, v[k], v[k - 1]);
+}
+
+// one step back: the state before sample x, from the state after it
+template <int K>
+__device__ __forceinline__ void cas_unstep(double inv_p, double (&v)[K], double x) {
+#pragma unroll
+    for (int k = K - 1; k >= 1; --k) v[k] = (v[k] - v[k - 1]) * inv_p;
+    v[0] = (v[0] - x) * inv_p;
 }
 
 // v <- A^n v + z, with pn = p^n
 template <int K>
-__device__ __forceinline__ void cas_advance_add(float pn, float n, float (&v)[K], const float (&z)[K]) {
-    const float a = v[0], b = v[1];
+__device__ __forceinline__ void cas_advance_add(double pn, double n, double (&v)[K], const double (&z)[K]) {
+    const double a = v[0], b = v[1];
     if constexpr (K == 3) {
-        const float c = v[2];
-        v[2] = fmaf(pn, fmaf(0.5f * n * (n + 1.0f), a, fmaf(n, b, c)), z[2]);
+        const double c = v[2];
+        v[2] = fma(pn, fma(0.5 * n * (n + 1.0), a, fma(n, b, c)), z[2]);
     }
-    v[1] = fmaf(pn, fmaf(n, a, b), z[1]);
-    v[0] = fmaf(pn, a, z[0]);
+    v[1] = fma(pn, fma(n, a, b), z[1]);
+    v[0] = fma(pn, a, z[0]);
 }
 
 template <int K>
-__device__ __forceinline__ void set_zero(float (&v)[K]) {
+__device__ __forceinline__ void set_zero(double (&v)[K]) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0f;
+    for (int k = 0; k < K; ++k) v[k] = 0.0;
 }
 
 // p^n for 0 <= n < 128 from the binary powers
-__device__ __forceinline__ float pow_bits(const ScaleArgs &c, int n) {
-    float r = 1.0f;
+__device__ __forceinline__ double pow_bits(const ScaleArgs &c, int n) {
+    double r = 1.0;
 #pragma unroll
     for (int k = 0; k < 7; ++k)
         if ((n >> k) & 1) r *= c.pbit[k];
     return r;
 }
 
-// p^(C m) for 0 <= m < 256 from the chunk powers
-__device__ __forceinline__ float pow_chunks(const ScaleArgs &c, int m) {
-    float r = 1.0f;
+// p^(C m) for 0 <= m < 128 from the chunk powers
+__device__ __forceinline__ double pow_chunks(const ScaleArgs &c, int m) {
+    double r = 1.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < 7; ++k)
         if ((m >> k) & 1) r *= c.pchunk[k];
     return r;
 }
@@ -124,7 +143,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     int64_t plane_stride, int H, int W, Args a) {
     constexpr int LP = C + 1;  // padded lane stride in LDS: conflict-free chunk reads
     __shared__ float buf[ROW_WPB][64 * LP];
-    __shared__ float tot[ROW_WPB][2][K];
+    __shared__ double tot[ROW_WPB][2][K];
 
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -146,15 +165,11 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     for (int i = 0; i < C; ++i) {
         const int j = i * 64 + lane;
         const int col = seg0 + j;
-        float v = 0.0f;
-        if (row_ok && col < W) v = load_as_float(src + col);
-        lds[j + j / C] = v;
+        const float v = load_as_float(src + min(col, W - 1));
+        lds[j + j / C] = (row_ok && col < W) ? v : 0.0f;
     }
-    float x_first = 0.0f, x_last = 0.0f;
-    if (row_ok) {
-        x_first = load_as_float(src);
-        x_last = load_as_float(src + (W - 1));
-    }
+    const double x_first = load_as_float(src);
+    const double x_last = load_as_float(src + (W - 1));
     __syncthreads();
     float xs[C];
 #pragma unroll
@@ -163,62 +178,60 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 
     for (int s = 0; s < a.nscales; ++s) {
         const ScaleArgs &cf = a.s[s];
-        const float p = cf.p;
-        const float nC = (float)C;
-        // ---- pass 1: zero-state chunk states
-        float zf[K], zb[K];
+        const double p = cf.p;
+        // ---- zero-state chunk states
+        double zf[K], zb[K];
         set_zero(zf);
         set_zero(zb);
 #pragma unroll
-        for (int j = 0; j < C; ++j) cas_step(p, zf, xs[j]);
+        for (int j = 0; j < C; ++j) cas_step(p, zf, (double)xs[j]);
 #pragma unroll
-        for (int j = C - 1; j >= 0; --j) cas_step(p, zb, xs[j]);
+        for (int j = C - 1; j >= 0; --j) cas_step(p, zb, (double)xs[j]);
 
-        float init_l[K], init_r[K];
+        double init_l[K], init_r[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            init_l[k] = a.boundary == FDVM_BC_REPLICATE ? x_first * cf.ss[k] : 0.0f;
-            init_r[k] = a.boundary == FDVM_BC_REPLICATE ? x_last * cf.ss[k] : 0.0f;
+            init_l[k] = a.boundary == FDVM_BC_REPLICATE ? x_first * cf.ss[k] : 0.0;
+            init_r[k] = a.boundary == FDVM_BC_REPLICATE ? x_last * cf.ss[k] : 0.0;
         }
-        // forward elements: w_0 absorbs the left start state
-        float sf[K];
+        // forward elements: chunk 0 absorbs the left start state
+        double sf[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) sf[k] = zf[k];
         if (g == 0) {
-            float t[K];
+            double t[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) t[k] = init_l[k];
-            cas_advance_add(cf.pchunk[0], nC, t, zf);
+            cas_advance_add(cf.pchunk[0], (double)C, t, zf);
 #pragma unroll
             for (int k = 0; k < K; ++k) sf[k] = t[k];
         }
         // backward elements: the chunk holding column W-1 absorbs the right
         // start state; chunks past the end contribute nothing
-        float sb[K];
+        double sb[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) sb[k] = g > g_last ? 0.0f : zb[k];
+        for (int k = 0; k < K; ++k) sb[k] = g > g_last ? 0.0 : zb[k];
         if (g == g_last) {
-            float t[K];
+            double t[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) t[k] = init_r[k];
-            cas_advance_add(pow_bits(cf, nv), (float)nv, t, zb);
+            cas_advance_add(pow_bits(cf, nv), (double)nv, t, zb);
 #pragma unroll
             for (int k = 0; k < K; ++k) sb[k] = t[k];
         }
-        // ---- intra-wavefront inclusive scans (forward: from the left,
-        // backward: from the right)
+        // ---- intra-wavefront inclusive scans (forward from the left,
+        // backward from the right): S_l <- A^(C d) S_(l-d) + S_l
 #pragma unroll
         for (int lvl = 0; lvl < 6; ++lvl) {
             const int d = 1 << lvl;
-            const float pn = cf.pchunk[lvl];
-            const float n = (float)(C * d);
-            float tf[K], tb[K];
+            const double pn = cf.pchunk[lvl];
+            const double n = (double)(C * d);
+            double tf[K], tb[K];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 tf[k] = __shfl_up(sf[k], d, 64);
                 tb[k] = __shfl_down(sb[k], d, 64);
             }
-            // S_l <- A^(C d) S_(l-d) + S_l   (and the mirror image)
             cas_advance_add(pn, n, tf, sf);
             cas_advance_add(pn, n, tb, sb);
 #pragma unroll
@@ -228,7 +241,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
             }
         }
         // ---- across the R wavefronts of the row
-        float cwf[K], cwb[K];  // state entering this wavefront's segment
+        double cwf[K], cwb[K];  // states entering this wavefront's segment
         set_zero(cwf);
         set_zero(cwb);
         if constexpr (R > 1) {
@@ -242,75 +255,80 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
             }
             __syncthreads();
             const int base = wv - r;
-            const float pn = cf.pchunk[6];
-            const float n = (float)(C * 64);
+            const double pn = cf.pchunk[6];
+            const double n = (double)(C * 64);
             for (int q = 0; q < r; ++q) {
-                float z[K];
+                double z[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) z[k] = tot[base + q][0][k];
                 cas_advance_add(pn, n, cwf, z);
             }
             for (int q = R - 1; q > r; --q) {
-                float z[K];
+                double z[K];
 #pragma unroll
                 for (int k = 0; k < K; ++k) z[k] = tot[base + q][1][k];
                 cas_advance_add(pn, n, cwb, z);
             }
             __syncthreads();
-            // fold the incoming segment state into the per-lane scans
-            float t1[K], t2[K];
+            double t1[K], t2[K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) { t1[k] = cwf[k]; t2[k] = cwb[k]; }
-            cas_advance_add(pow_chunks(cf, lane + 1), (float)(C * (lane + 1)), t1, sf);
-            cas_advance_add(pow_chunks(cf, 64 - lane), (float)(C * (64 - lane)), t2, sb);
+            for (int k = 0; k < K; ++k) {
+                t1[k] = cwf[k];
+                t2[k] = cwb[k];
+            }
+            cas_advance_add(pow_chunks(cf, lane + 1), (double)(C * (lane + 1)), t1, sf);
+            cas_advance_add(pow_chunks(cf, 64 - lane), (double)(C * (64 - lane)), t2, sb);
 #pragma unroll
-            for (int k = 0; k < K; ++k) { sf[k] = t1[k]; sb[k] = t2[k]; }
+            for (int k = 0; k < K; ++k) {
+                sf[k] = t1[k];
+                sb[k] = t2[k];
+            }
         }
         // carry into each chunk: exclusive scans
-        float vf[K], vb[K];
+        double vf[K], vb[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const float up = __shfl_up(sf[k], 1, 64);
-            const float dn = __shfl_down(sb[k], 1, 64);
+            const double up = __shfl_up(sf[k], 1, 64);
+            const double dn = __shfl_down(sb[k], 1, 64);
             vf[k] = lane == 0 ? cwf[k] : up;
             vb[k] = lane == 63 ? cwb[k] : dn;
             if (g == 0) vf[k] = init_l[k];
             if (g == g_last) vb[k] = init_r[k];
         }
-        // ---- pass 2: final outputs of the chunk
-        float ys[C];
+        // ---- final outputs of the chunk
+        double ys[C];
         if (full_wave) {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
-                ys[j] = fmaf(cf.b0, xs[j], cas_out(cf, vb));
-                cas_step(p, vb, xs[j]);
+                ys[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                cas_step(p, vb, (double)xs[j]);
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 ys[j] += cas_out(cf, vf);
-                cas_step(p, vf, xs[j]);
+                cas_step(p, vf, (double)xs[j]);
             }
         } else {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
                 if (j < nv) {
-                    ys[j] = fmaf(cf.b0, xs[j], cas_out(cf, vb));
-                    cas_step(p, vb, xs[j]);
+                    ys[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                    cas_step(p, vb, (double)xs[j]);
                 } else {
-                    ys[j] = 0.0f;
+                    ys[j] = 0.0;
                 }
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 if (j < nv) {
                     ys[j] += cas_out(cf, vf);
-                    cas_step(p, vf, xs[j]);
+                    cas_step(p, vf, (double)xs[j]);
                 }
             }
         }
         // ---- back through LDS to coalesced stores
 #pragma unroll
-        for (int j = 0; j < C; ++j) lds[lane * LP + j] = ys[j];
+        for (int j = 0; j < C; ++j) lds[lane * LP + j] = (float)ys[j];
         __syncthreads();
         float *dst = out + (int64_t)s * plane_stride + (int64_t)(row_ok ? row : 0) * out_pitch;
 #pragma unroll 4
@@ -324,179 +342,223 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 }
 
 // ------------------------------------------------------------ column pass
+// (a) zero-state end states of every 64-row tile.  st layout:
+//     st[((s * nty + ty) * 2K + k) * W + x], k < K forward, k >= K backward.
 template <int K>
-__global__ __launch_bounds__(COL_NW * 64) void iir_cols_kernel(
-    const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out, int64_t pitch,
-    int64_t plane_stride, int H, int W, int seg, Args a) {
-    constexpr int TW = COL_TW;
-    extern __shared__ float tst[];            // [COL_NW][ntmax][K][64]
-    __shared__ float xz[COL_NW][2][K][64];
-
+__global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
+    const float *__restrict__ in, int64_t pitch, int64_t plane_stride, int H, int W, int nty,
+    float *__restrict__ st, Args a) {
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
-    const int s = blockIdx.y;
+    const int ty = blockIdx.y * COL_WPB + (threadIdx.x >> 6);
+    const int s = blockIdx.z;
     const int col = blockIdx.x * 64 + lane;
-    const bool col_ok = col < W;
-    const int ccol = col_ok ? col : W - 1;
+    if (ty >= nty) return;
+    const int ccol = min(col, W - 1);
     const ScaleArgs &cf = a.s[s];
-    const float p = cf.p;
-    const int ntmax = seg / TW;
-    const float *plane = in + (int64_t)s * in_plane_stride;   // read with in_pitch
-    float *oplane = out + (int64_t)s * plane_stride;          // written with pitch
-
-    const int r0 = wv * seg;
-    const int r1 = min(r0 + seg, H);
-    const int len = max(0, r1 - r0);
-    const int nt = (len + TW - 1) / TW;
-    float *my = tst + (size_t)wv * ntmax * K * 64;
-
-    // ---- pass 1: zero-state states per tile and per segment
-    float zf[K];
+    const double p = cf.p;
+    const int y0 = ty * CT;
+    const float *plane = in + (int64_t)s * plane_stride + ccol;
+    float xs[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) {
+        const int y = y0 + j;
+        const float v = plane[(int64_t)min(y, H - 1) * pitch];
+        xs[j] = y < H ? v : 0.0f;  // zeros after the last row leave the
+    }                              // backward zero state exact
+    double zf[K], zb[K];
     set_zero(zf);
-    for (int t = 0; t < nt; ++t) {
-        const int rt = r0 + t * TW;
-        const int lt = min(TW, r1 - rt);
-        float xs[TW];
+    set_zero(zb);
 #pragma unroll
-        for (int j = 0; j < TW; ++j)
-            xs[j] = (j < lt) ? plane[(int64_t)(rt + j) * in_pitch + ccol] : 0.0f;
+    for (int j = 0; j < CT; ++j) cas_step(p, zf, (double)xs[j]);
 #pragma unroll
-        for (int j = 0; j < TW; ++j) cas_step(p, zf, xs[j]);
-        float u[K];
-        set_zero(u);
-#pragma unroll
-        for (int j = TW - 1; j >= 0; --j) cas_step(p, u, xs[j]);
-#pragma unroll
-        for (int k = 0; k < K; ++k) my[(t * K + k) * 64 + lane] = u[k];
-    }
-    {
-        float acc[K];
-        set_zero(acc);
-        for (int t = nt - 1; t >= 0; --t) {
-            float u[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) u[k] = my[(t * K + k) * 64 + lane];
-            cas_advance_add(cf.pbit[6], (float)TW, acc, u);
-        }
+    for (int j = CT - 1; j >= 0; --j) cas_step(p, zb, (double)xs[j]);
+    if (col < W) {
+        float *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + col;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            xz[wv][0][k][lane] = zf[k];
-            xz[wv][1][k][lane] = acc[k];
-        }
-    }
-    __syncthreads();
-
-    // ---- carries entering this segment from above (forward) and below
-    const float x_top = plane[ccol];
-    const float x_bot = plane[(int64_t)(H - 1) * in_pitch + ccol];
-    float cfw[K], cbw[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        cfw[k] = a.boundary == FDVM_BC_REPLICATE ? x_top * cf.ss[k] : 0.0f;
-        cbw[k] = a.boundary == FDVM_BC_REPLICATE ? x_bot * cf.ss[k] : 0.0f;
-    }
-    for (int q = 0; q < wv; ++q) {
-        float z[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) z[k] = xz[q][0][k][lane];
-        cas_advance_add(cf.pseg, (float)seg, cfw, z);
-    }
-    const int last = (H - 1) / seg;  // last segment holding data
-    if (wv < last) {
-        // through the (possibly short) last segment first
-        const int lenL = H - last * seg;
-        float pL = 1.0f;
-        {
-            int n = lenL;
-            int full = n / TW;
-            for (int i = 0; i < full; ++i) pL *= cf.pbit[6];
-            pL *= pow_bits(cf, n - full * TW);
-        }
-        float z[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) z[k] = xz[last][1][k][lane];
-        cas_advance_add(pL, (float)lenL, cbw, z);
-        for (int q = last - 1; q > wv; --q) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) z[k] = xz[q][1][k][lane];
-            cas_advance_add(cf.pseg, (float)seg, cbw, z);
-        }
-    }
-    // true backward state at the bottom edge of every tile
-    {
-        float acc[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] = cbw[k];
-        for (int t = nt - 1; t >= 0; --t) {
-            const int lt = min(TW, r1 - (r0 + t * TW));
-            float u[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                u[k] = my[(t * K + k) * 64 + lane];
-                my[(t * K + k) * 64 + lane] = acc[k];
-            }
-            cas_advance_add(lt == TW ? cf.pbit[6] : pow_bits(cf, lt), (float)lt, acc, u);
-        }
-    }
-
-    // ---- pass 2
-    float vf[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) vf[k] = cfw[k];
-    for (int t = 0; t < nt; ++t) {
-        const int rt = r0 + t * TW;
-        const int lt = min(TW, r1 - rt);
-        float xs[TW], ys[TW];
-        float vb[K];
-#pragma unroll
-        for (int k = 0; k < K; ++k) vb[k] = my[(t * K + k) * 64 + lane];
-        if (lt == TW) {
-#pragma unroll
-            for (int j = 0; j < TW; ++j) xs[j] = plane[(int64_t)(rt + j) * in_pitch + ccol];
-#pragma unroll
-            for (int j = TW - 1; j >= 0; --j) {
-                ys[j] = fmaf(cf.b0, xs[j], cas_out(cf, vb));
-                cas_step(p, vb, xs[j]);
-            }
-#pragma unroll
-            for (int j = 0; j < TW; ++j) {
-                ys[j] += cas_out(cf, vf);
-                cas_step(p, vf, xs[j]);
-            }
-            if (col_ok) {
-#pragma unroll
-                for (int j = 0; j < TW; ++j) oplane[(int64_t)(rt + j) * pitch + col] = ys[j];
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < TW; ++j)
-                xs[j] = (j < lt) ? plane[(int64_t)(rt + j) * in_pitch + ccol] : 0.0f;
-#pragma unroll
-            for (int j = TW - 1; j >= 0; --j) {
-                if (j < lt) {
-                    ys[j] = fmaf(cf.b0, xs[j], cas_out(cf, vb));
-                    cas_step(p, vb, xs[j]);
-                } else {
-                    ys[j] = 0.0f;
-                }
-            }
-#pragma unroll
-            for (int j = 0; j < TW; ++j) {
-                if (j < lt) {
-                    ys[j] += cas_out(cf, vf);
-                    cas_step(p, vf, xs[j]);
-                }
-            }
-            if (col_ok) {
-#pragma unroll
-                for (int j = 0; j < TW; ++j)
-                    if (j < lt) oplane[(int64_t)(rt + j) * pitch + col] = ys[j];
-            }
+            o[(int64_t)k * W] = (float)zf[k];
+            o[(int64_t)(K + k) * W] = (float)zb[k];
         }
     }
 }
 
-Args make_args(const IirParams &prm, int C, int seg) {
+// (b) carries: in place, every tile's forward zero state becomes the forward
+// state entering the tile from above, every backward zero state the backward
+// state entering it from below.
+template <int K>
+__global__ __launch_bounds__(256) void iir_col_scan_kernel(const float *__restrict__ in, int64_t pitch,
+                                                           int64_t plane_stride, int H, int W, int nty,
+                                                           float *__restrict__ st, Args a) {
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int s = blockIdx.y;
+    if (col >= W) return;
+    const ScaleArgs &cf = a.s[s];
+    const float *plane = in + (int64_t)s * plane_stride + col;
+    const bool rep = a.boundary == FDVM_BC_REPLICATE;
+    const double x_top = plane[0];
+    const double x_bot = plane[(int64_t)(H - 1) * pitch];
+    float *base = st + (int64_t)s * nty * 2 * K * W + col;
+    double c[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = rep ? x_top * cf.ss[k] : 0.0;
+    const double pt = cf.pbit[6];  // p^64
+    for (int ty = 0; ty < nty; ++ty) {
+        float *o = base + (int64_t)ty * 2 * K * W;
+        double z[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            z[k] = o[(int64_t)k * W];
+            o[(int64_t)k * W] = (float)c[k];
+        }
+        cas_advance_add(pt, (double)CT, c, z);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) c[k] = rep ? x_bot * cf.ss[k] : 0.0;
+    for (int ty = nty - 1; ty >= 0; --ty) {
+        float *o = base + (int64_t)ty * 2 * K * W;
+        double z[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            z[k] = o[(int64_t)(K + k) * W];
+            o[(int64_t)(K + k) * W] = (float)c[k];
+        }
+        const int len = min(CT, H - ty * CT);
+        cas_advance_add(len == CT ? pt : pow_bits(cf, len), (double)len, c, z);
+    }
+}
+
+// (c) final pass of one 64-row tile per wavefront.  LAP = false: writes the
+// blur; in place is allowed (a tile reads and writes only its own rows).
+// LAP = true: writes sigma^2 (D20 + D02) of the blur; lanes cover columns
+// x0 - 1 .. x0 + 62 and lanes 1..62 write (in and out must not overlap).
+template <int K, bool LAP>
+__global__ __launch_bounds__(COL_WPB * 64) void iir_col_final_kernel(
+    const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out, int64_t out_pitch,
+    int64_t out_plane_stride, int H, int W, int nty, const float *__restrict__ st, Args a) {
+    const int lane = threadIdx.x & 63;
+    const int ty = blockIdx.y * COL_WPB + (threadIdx.x >> 6);
+    const int s = blockIdx.z;
+    const int col = LAP ? blockIdx.x * 62 - 1 + lane : blockIdx.x * 64 + lane;
+    if (ty >= nty) return;
+    const int ccol = min(max(col, 0), W - 1);
+    const ScaleArgs &cf = a.s[s];
+    const double p = cf.p;
+    const int y0 = ty * CT;
+    const int y1 = min(y0 + CT, H);
+    const int len = y1 - y0;
+    const float *plane = in + (int64_t)s * in_plane_stride + ccol;
+    float xs[CT];
+#pragma unroll
+    for (int j = 0; j < CT; ++j) xs[j] = plane[(int64_t)min(y0 + j, H - 1) * in_pitch];
+    double vf[K], vb[K];
+    {
+        const float *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + ccol;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            vf[k] = o[(int64_t)k * W];
+            vb[k] = o[(int64_t)(K + k) * W];
+        }
+    }
+    float *dst = out + (int64_t)s * out_plane_stride;
+    double t[CT];
+    // ---- backward sweep: t(n) = y-(n) + b0 x(n)
+    double t_bot = 0.0;
+    if (LAP && y1 < H) {
+        const double xb = plane[(int64_t)y1 * in_pitch];
+        double u[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) u[k] = vb[k];
+        cas_unstep(cf.inv_p, u, xb);  // state before row y1 (from below)
+        t_bot = fma(cf.b0, xb, cas_out(cf, u));
+    }
+    if (len == CT) {
+#pragma unroll
+        for (int j = CT - 1; j >= 0; --j) {
+            t[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+            cas_step(p, vb, (double)xs[j]);
+        }
+    } else {
+#pragma unroll
+        for (int j = CT - 1; j >= 0; --j) {
+            if (j < len) {
+                t[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                cas_step(p, vb, (double)xs[j]);
+            } else {
+                t[j] = 0.0;
+            }
+        }
+    }
+    if constexpr (!LAP) {
+        // ---- forward sweep and output
+        if (len == CT) {
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                const double y = t[j] + cas_out(cf, vf);
+                cas_step(p, vf, (double)xs[j]);
+                if (col < W) dst[(int64_t)(y0 + j) * out_pitch + col] = (float)y;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < CT; ++j) {
+                if (j < len) {
+                    const double y = t[j] + cas_out(cf, vf);
+                    cas_step(p, vf, (double)xs[j]);
+                    if (col < W) dst[(int64_t)(y0 + j) * out_pitch + col] = (float)y;
+                }
+            }
+        }
+    } else {
+        // the row above the tile: y-(y0-1) = W u(y0) with u(y0) = vb now
+        double b_top = 0.0;
+        if (y0 > 0) {
+            const double xa = plane[(int64_t)(y0 - 1) * in_pitch];
+            const double ta = fma(cf.b0, xa, cas_out(cf, vb));
+            double v[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) v[k] = vf[k];
+            cas_unstep(cf.inv_p, v, xa);  // forward state before row y0-1
+            b_top = ta + cas_out(cf, v);
+        }
+        const double sig2 = cf.sig2;
+        const bool wr = lane >= 1 && lane <= 62 && col < W;
+        // sliding rows: bm = B(n-1), bc = B(n); V(n) needs B(n+1)
+        double bc = t[0] + cas_out(cf, vf);
+        cas_step(p, vf, (double)xs[0]);
+        double bm = y0 > 0 ? b_top : bc;
+        auto emit = [&](int y, double bmv, double bcv, double bnv) {
+            const double bl = __shfl_up(bcv, 1, 64);
+            const double br = __shfl_down(bcv, 1, 64);
+            const double v = sig2 * ((bl - bcv) + (br - bcv) + (bmv - bcv) + (bnv - bcv));
+            if (wr) dst[(int64_t)y * out_pitch + col] = (float)v;
+        };
+        if (len == CT) {
+#pragma unroll
+            for (int j = 1; j < CT; ++j) {
+                const double bn = t[j] + cas_out(cf, vf);
+                cas_step(p, vf, (double)xs[j]);
+                emit(y0 + j - 1, bm, bc, bn);
+                bm = bc;
+                bc = bn;
+            }
+        } else {
+#pragma unroll
+            for (int j = 1; j < CT; ++j) {
+                if (j < len) {
+                    const double bn = t[j] + cas_out(cf, vf);
+                    cas_step(p, vf, (double)xs[j]);
+                    emit(y0 + j - 1, bm, bc, bn);
+                    bm = bc;
+                    bc = bn;
+                }
+            }
+        }
+        // the row below the tile: B(y1) = y-(y1) + b0 x(y1) + y+(y1), y+(y1) = W v(y1 - 1)
+        const double bn = y1 < H ? t_bot + cas_out(cf, vf) : bc;
+        emit(y1 - 1, bm, bc, bn);
+    }
+}
+
+Args make_args(const IirParams &prm, int C) {
     Args a{};
     a.nscales = prm.nscales;
     a.boundary = prm.boundary;
@@ -504,14 +566,17 @@ Args make_args(const IirParams &prm, int C, int seg) {
         const IirScaleParams &q = prm.s[s];
         ScaleArgs &d = a.s[s];
         d.p = q.p;
+        d.inv_p = 1.0 / q.p;
         d.b0 = q.b0;
+        d.sig2 = q.sig2;
         for (int k = 0; k < 3; ++k) {
             d.w[k] = q.w[k];
             d.ss[k] = q.ss[k];
         }
-        for (int k = 0; k < 7; ++k) d.pbit[k] = (float)std::exp((double)(1 << k) * q.lnp);
-        for (int k = 0; k < 8; ++k) d.pchunk[k] = (float)std::exp((double)C * (double)(1 << k) * q.lnp);
-        d.pseg = (float)std::exp((double)seg * q.lnp);
+        for (int k = 0; k < 7; ++k) {
+            d.pbit[k] = std::exp((double)(1 << k) * q.lnp);
+            d.pchunk[k] = std::exp((double)C * (double)(1 << k) * q.lnp);
+        }
     }
     return a;
 }
@@ -519,7 +584,7 @@ Args make_args(const IirParams &prm, int C, int seg) {
 template <int K, int C, int R, typename T>
 hipError_t launch_rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, float *out,
                          int64_t out_pitch, int64_t plane_stride, const IirParams &prm, hipStream_t st) {
-    Args a = make_args(prm, C, 0);
+    Args a = make_args(prm, C);
     const int rows_per_block = ROW_WPB / R;
     dim3 grid((unsigned)((H + rows_per_block - 1) / rows_per_block));
     hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T>), grid, dim3(ROW_WPB * 64), 0, st,
@@ -542,6 +607,35 @@ hipError_t launch_rows_k(const void *in, int64_t H, int64_t W, int64_t in_pitch,
     return hipErrorInvalidValue;
 }
 
+template <int K>
+hipError_t launch_cols_k(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
+                         int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool lap,
+                         const IirParams &prm, float *st, hipStream_t stream) {
+    Args a = make_args(prm, 1);
+    const int nty = (int)((H + CT - 1) / CT);
+    const unsigned S = (unsigned)prm.nscales;
+    dim3 g1((unsigned)((W + 63) / 64), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
+    hipLaunchKernelGGL((iir_col_states_kernel<K>), g1, dim3(COL_WPB * 64), 0, stream, in, in_pitch,
+                       in_plane_stride, (int)H, (int)W, nty, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    dim3 g2((unsigned)((W + 255) / 256), S);
+    hipLaunchKernelGGL((iir_col_scan_kernel<K>), g2, dim3(256), 0, stream, in, in_pitch, in_plane_stride,
+                       (int)H, (int)W, nty, st, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (lap) {
+        dim3 g3((unsigned)((W + 61) / 62), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
+        hipLaunchKernelGGL((iir_col_final_kernel<K, true>), g3, dim3(COL_WPB * 64), 0, stream, in, in_pitch,
+                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, nty, st, a);
+    } else {
+        dim3 g3((unsigned)((W + 63) / 64), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
+        hipLaunchKernelGGL((iir_col_final_kernel<K, false>), g3, dim3(COL_WPB * 64), 0, stream, in, in_pitch,
+                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, nty, st, a);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
@@ -561,31 +655,22 @@ hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int6
     return hipErrorInvalidValue;
 }
 
-size_t iir_cols_lds_bytes(int64_t H, int order, int *seg_out) {
-    const int64_t per = (H + COL_NW - 1) / COL_NW;
-    const int seg = (int)(((per + COL_TW - 1) / COL_TW) * COL_TW);
-    if (seg_out) *seg_out = seg;
-    return (size_t)COL_NW * (seg / COL_TW) * order * 64 * sizeof(float);
+size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order) {
+    const int64_t nty = (H + CT - 1) / CT;
+    return ((size_t)nscales * nty * 2 * order * W * sizeof(float) + 255) & ~(size_t)255;
 }
 
 hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
-                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
-                           const IirParams &prm, hipStream_t st) {
-    int seg = 0;
-    const size_t lds = iir_cols_lds_bytes(H, prm.order, &seg);
-    if (lds > 120 * 1024) return hipErrorInvalidValue;
-    Args a = make_args(prm, 1, seg);
-    dim3 grid((unsigned)((W + 63) / 64), (unsigned)prm.nscales);
-    if (prm.order == 3) {
-        hipLaunchKernelGGL((iir_cols_kernel<3>), grid, dim3(COL_NW * 64), lds, st, in, in_pitch,
-                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, seg, a);
-    } else if (prm.order == 2) {
-        hipLaunchKernelGGL((iir_cols_kernel<2>), grid, dim3(COL_NW * 64), lds, st, in, in_pitch,
-                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, seg, a);
-    } else {
-        return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool laplacian,
+                           const IirParams &prm, void *ws, hipStream_t st) {
+    float *states = static_cast<float *>(ws);
+    if (prm.order == 3)
+        return launch_cols_k<3>(in, in_pitch, in_plane_stride, out, H, W, pitch, plane_stride, laplacian, prm,
+                                states, st);
+    if (prm.order == 2)
+        return launch_cols_k<2>(in, in_pitch, in_plane_stride, out, H, W, pitch, plane_stride, laplacian, prm,
+                                states, st);
+    return hipErrorInvalidValue;
 }
 
 }  // namespace fdvm

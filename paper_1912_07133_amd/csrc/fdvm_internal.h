@@ -14,19 +14,19 @@ namespace fdvm {
 // e = 1 - p is passed separately so it keeps full relative precision.
 void repeated_pole_de(int K, double p, double e, double *b0, double bp[4], double ap[4]);
 
-// Float32 realisation of the repeated-pole blur as a cascade of K first-order
-// sections sharing the pole p32 = fl32(p):
-//   v_1(n) = p32 v_1(n-1) + x(n),  v_k(n) = p32 v_k(n-1) + v_{k-1}(n),
+// Realisation of the repeated-pole blur as a cascade of K first-order
+// sections sharing the pole p (float64):
+//   v_1(n) = p v_1(n-1) + x(n),  v_k(n) = p v_k(n-1) + v_{k-1}(n),
 //   y+(n)  = sum_k w[k-1] v_k(n-1)          (causal part of Eq A10a)
-// and the mirror image for the anti-causal part; w and b0 are the float64
-// design at p32 rounded once.  ss[k-1] = 1/(1 - p32)^k is the steady-state
-// value of v_k for a unit constant input (Eq A32 read as replicate extension).
+// and the mirror image for the anti-causal part.  ss[k-1] = 1/(1 - p)^k is
+// the steady-state value of v_k for a unit constant input (Eq A32 read as
+// replicate extension).
 struct Cascade {
-    float p;
-    float b0;
-    float w[3];
-    float ss[3];
-    double lnp;  // log(p32), for p32^n at run-time lengths
+    double p;
+    double b0;
+    double w[3];
+    double ss[3];
+    double lnp;  // log(p), for p^n at run-time lengths
 };
 Cascade cascade_realisation(int K, double sigma);
 
@@ -35,15 +35,12 @@ int colored_sg_taps(double sigma, int K, double omega_c, double *taps);
 int gaussian_taps(double sigma, int K, double *taps);
 
 // ---------------------------------------------------------------- kernels
-constexpr int IIR_TILE = 32;  // samples per tile along the recursion
-
 struct IirScaleParams {
-    float p, b0;
-    float w[3];
-    float ss[3];
-    float p_tile;  // p^IIR_TILE
-    float pad;
+    double p, b0;
+    double w[3];
+    double ss[3];
     double lnp;
+    double sig2;  // sigma^2, for the fused normalised Laplacian
 };
 
 struct IirParams {
@@ -57,9 +54,10 @@ struct IirParams {
 hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
                            float *out, int64_t out_pitch, int64_t plane_stride,
                            const IirParams &prm, hipStream_t stream);
+size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order);
 hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
-                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
-                           const IirParams &prm, hipStream_t stream);
+                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool laplacian,
+                           const IirParams &prm, void *ws, hipStream_t stream);
 
 hipError_t launch_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                            int nscales, const float *norms, unsigned what,

@@ -93,19 +93,25 @@ def test_device_calls_validate_on_the_host():
     assert L.fdvm_filter_design(0, 3, 4.0, 0, ctypes.byref(f), None, 0) == P.OK
     fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
     filt = (P.Filter * 1)(f)
-    assert L.fdvm_blur_iir(None, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
-    assert L.fdvm_blur_iir(fake, P.F32, 0, 8, 8, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
-    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 4, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
-    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 0, 0, None) == P.EINVAL
-    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 17, 0, None) == P.EINVAL
-    assert L.fdvm_blur_iir(fake, 9, 8, 8, 8, fake, 8, 64, filt, 1, 0, None) == P.EINVAL
-    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 5, None) == P.EINVAL
+    assert L.fdvm_blur_iir(None, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 0, 8, 8, fake, 8, 64, filt, 1, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 4, fake, 8, 64, filt, 1, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 0, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 17, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, 9, 8, 8, 8, fake, 8, 64, filt, 1, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 5, fake, 1 << 30, None) == P.EINVAL
     two = (P.Filter * 2)(f, f)
-    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 10, two, 2, 0, None) == P.EINVAL  # stride
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 10, two, 2, 0, fake, 1 << 30, None) == P.EINVAL  # stride
     f2 = P.Filter()
     assert L.fdvm_filter_design(0, 2, 4.0, 0, ctypes.byref(f2), None, 0) == P.OK
     mixed = (P.Filter * 2)(f, f2)
-    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, mixed, 2, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, mixed, 2, 0, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 0, None, 0, None) == P.EINVAL
+    assert L.fdvm_blur_iir(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 0, fake, 16, None) == P.ENOMEM
+    assert L.fdvm_iir_laplacian(fake, P.F32, 8, 8, 8, fake, 8, 64, filt, 1, 0, fake, 16, None) == P.ENOMEM
+    assert L.fdvm_iir_pass(fake, P.U16, 8, 8, 8, 64, fake, 8, 64, filt, 1, 0, 1, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_iir_pass(fake, P.F32, 8, 8, 8, 64, fake, 8, 64, filt, 1, 0, 2, fake, 1 << 30, None) == P.EINVAL
+    assert L.fdvm_iir_pass(fake, P.F32, 8, 8, 8, 64, fake, 8, 64, filt, 1, 0, 3, fake, 1 << 30, None) == P.EINVAL
     sig = (ctypes.c_double * 1)(2.0)
     assert L.fdvm_highpass(fake, 8, 8, 8, 64, 1, sig, 0, 1, fake, 64, None) == P.EINVAL
     assert L.fdvm_highpass(fake, 8, 8, 8, 64, 1, sig, 64, 1, fake, 64, None) == P.EINVAL
@@ -122,6 +128,7 @@ def test_device_calls_validate_on_the_host():
 
 
 def test_workspace_sizes():
-    assert P.workspace_bytes(P.OP_BLUR_IIR, 2048, 2048, 8) == 0
+    assert P.workspace_bytes(P.OP_BLUR_IIR, 2048, 2048, 8) >= 8 * 32 * 6 * 2048 * 4
+    assert P.workspace_bytes(P.OP_IIR_LAPLACIAN, 2048, 2048, 8) >= 8 * 2048 * 2048 * 4
     assert P.workspace_bytes(P.OP_BLUR_FIR, 2048, 2048, 8, 192) >= 2048 * 2048 * 4
     assert P.workspace_bytes(P.OP_DETECT, 2048, 2048, 8) >= 8 * 2048 * (2048 // 64) * 8

@@ -113,3 +113,63 @@ def test_deterministic_run_to_run():
     a = P.blur_iir(x, [2.0, 20.0], order=3)
     b = P.blur_iir(x, [2.0, 20.0], order=3)
     assert torch.equal(a, b)
+
+
+# ----------------------------------------------------------------- fused V
+def oracle_v(x64, sigmas, order, boundary):
+    from oracle import shape
+    return shape.laplacian_bank(oracle_bank(x64, sigmas, order, boundary), sigmas)
+
+
+def v_error(got, ref):
+    """max |V_gpu - V_ref| relative to max |V_ref|, per plane."""
+    return [float(np.max(np.abs(got[s] - ref[s])) / max(np.max(np.abs(ref[s])), 1e-30))
+            for s in range(ref.shape[0])]
+
+
+# V is a second difference of B scaled by sigma^2; its float32 error floor is
+# the rounding of the x-pass planes (stored as float32) seen through the
+# stencil.  1e-5 of max |V| holds with an order of magnitude to spare.
+RTOL_V = 1e-5
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 70), (70, 2), (63, 62), (64, 64), (65, 125), (130, 300),
+                                   (257, 2100)])
+@pytest.mark.parametrize("order", [2, 3])
+def test_fused_laplacian_ragged(shape, order):
+    H, W = shape
+    say(f"case: fused laplacian {H}x{W} K={order}")
+    rng = np.random.default_rng(H * 31 + W)
+    img = rng.random((H, W)) * 200 + np.linspace(0, 30, W)[None, :]
+    sigmas = [0.6, 2.5, 17.0]
+    for bc in ("replicate", "zero"):
+        x, x64 = to_dev(img, "f32")
+        got = P.iir_laplacian(x, sigmas, order=order, boundary=bc).cpu().numpy()
+        err = v_error(got, oracle_v(x64, sigmas, order, bc))
+        assert max(err) <= RTOL_V, (bc, err)
+
+
+def test_fused_laplacian_full_frame():
+    cfg = syn.FULL_FRAME
+    say("case: fused laplacian full frame 2048x2048 u16 8 scales")
+    frame = syn.aerial_frame(cfg["H"], cfg["W"], cfg["seed"])
+    x, x64 = to_dev(frame, "u16")
+    got = P.iir_laplacian(x, cfg["sigmas"], order=3).cpu().numpy()
+    err = v_error(got, oracle_v(x64, cfg["sigmas"], 3, "replicate"))
+    say(f"   V errors {['%.1e' % e for e in err]}")
+    assert max(err) <= RTOL_V
+
+
+def test_pass_api_matches_blur():
+    say("case: iir_pass axis 0 + axis 1 == blur_iir; axis 2 == iir_laplacian")
+    frame = syn.aerial_frame(300, 500, 4)
+    x, _ = to_dev(frame, "u16")
+    sig = [1.0, 5.0, 30.0]
+    rows = P.iir_pass(x, sig, axis=0)
+    B = P.iir_pass(rows, sig, axis=1)
+    assert torch.equal(B, P.blur_iir(x, sig))
+    rows2 = P.iir_pass(x, sig, axis=0)
+    P.iir_pass(rows2, sig, axis=1, out=rows2)        # in place
+    assert torch.equal(rows2, B)
+    V = P.iir_pass(P.iir_pass(x, sig, axis=0), sig, axis=2)
+    assert torch.equal(V, P.iir_laplacian(x, sig))

@@ -66,8 +66,9 @@ def test_tiny_seeds_multi_scale(seed):
 
 def test_full_frame_end_to_end():
     """2048x2048 uint16, 8 scales, order 3: blur planes everywhere within
-    1e-5, Laplacian planes within the stencil-gain bound, detection sets equal
-    outside the fragile set."""
+    1e-5, and the detection lists of both GPU routes (fused blur + Laplacian,
+    and blur then high-pass) equal the oracle's outside the fragile set, which
+    must stay a small fraction of the pixels."""
     cfg = syn.FULL_FRAME
     say("case: full frame end-to-end")
     frame = syn.aerial_frame(cfg["H"], cfg["W"], cfg["seed"])
@@ -75,14 +76,14 @@ def test_full_frame_end_to_end():
     B_ref, V_ref, det_ref = run_oracle(f64, cfg["sigmas"], 3, cfg["tau"])
     x = torch.from_numpy(frame.view(np.int16)).cuda()
     B = P.blur_iir(x, cfg["sigmas"], order=3)
-    V = P.highpass(B, cfg["sigmas"])
-    det = P.detect_blobs(V, cfg["tau"], cfg["border"])
     assert_planes_close(B.cpu().numpy(), B_ref)
-    Vn = V.cpu().numpy()
-    for s, sigma in enumerate(cfg["sigmas"]):
-        bound = RTOL_BLUR * sigma ** 2 * 8 * np.max(np.abs(B_ref[s]))
-        assert np.max(np.abs(Vn[s] - V_ref[s])) <= bound
-    nfrag, mism = compare_detections(det, det_ref, V_ref, Vn, cfg["tau"])
-    say(f"   detections gpu={len(det)} ref={len(det_ref)} fragile={nfrag}")
-    assert mism == []
+    routes = {"fused": P.iir_laplacian(x, cfg["sigmas"], order=3), "two-step": P.highpass(B, cfg["sigmas"])}
+    for name, V in routes.items():
+        det = P.detect_blobs(V, cfg["tau"], cfg["border"])
+        Vn = V.cpu().numpy()
+        nfrag, mism = compare_detections(det, det_ref, V_ref, Vn, cfg["tau"])
+        say(f"   {name}: detections gpu={len(det)} ref={len(det_ref)} fragile={nfrag}")
+        assert mism == []
+        assert nfrag <= 1e-3 * Vn.size
+        assert abs(len(det) - len(det_ref)) <= max(5, 0.01 * len(det_ref))
     assert len(det_ref) > 10
