@@ -342,12 +342,12 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 }
 
 // ------------------------------------------------------------ column pass
-// (a) zero-state end states of every 64-row tile.  st layout:
+// (a) zero-state end states of every 64-row tile (float64).  st layout:
 //     st[((s * nty + ty) * 2K + k) * W + x], k < K forward, k >= K backward.
 template <int K>
 __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
     const float *__restrict__ in, int64_t pitch, int64_t plane_stride, int H, int W, int nty,
-    float *__restrict__ st, Args a) {
+    double *__restrict__ st, Args a) {
     const int lane = threadIdx.x & 63;
     const int ty = blockIdx.y * COL_WPB + (threadIdx.x >> 6);
     const int s = blockIdx.z;
@@ -373,11 +373,11 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
 #pragma unroll
     for (int j = CT - 1; j >= 0; --j) cas_step(p, zb, (double)xs[j]);
     if (col < W) {
-        float *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + col;
+        double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + col;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            o[(int64_t)k * W] = (float)zf[k];
-            o[(int64_t)(K + k) * W] = (float)zb[k];
+            o[(int64_t)k * W] = zf[k];
+            o[(int64_t)(K + k) * W] = zb[k];
         }
     }
 }
@@ -388,42 +388,41 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
 template <int K>
 __global__ __launch_bounds__(256) void iir_col_scan_kernel(const float *__restrict__ in, int64_t pitch,
                                                            int64_t plane_stride, int H, int W, int nty,
-                                                           float *__restrict__ st, Args a) {
+                                                           double *__restrict__ st, Args a) {
+    constexpr int U = 4;  // tiles whose states are fetched together
     const int col = blockIdx.x * 256 + threadIdx.x;
     const int s = blockIdx.y;
+    const int dir = blockIdx.z;  // 0: forward from the top, 1: backward from the bottom
     if (col >= W) return;
     const ScaleArgs &cf = a.s[s];
     const float *plane = in + (int64_t)s * plane_stride + col;
     const bool rep = a.boundary == FDVM_BC_REPLICATE;
-    const double x_top = plane[0];
-    const double x_bot = plane[(int64_t)(H - 1) * pitch];
-    float *base = st + (int64_t)s * nty * 2 * K * W + col;
+    const double xe = dir == 0 ? (double)plane[0] : (double)plane[(int64_t)(H - 1) * pitch];
+    double *base = st + (int64_t)s * nty * 2 * K * W + (int64_t)dir * K * W + col;
+    const int64_t tstride = (int64_t)2 * K * W;
     double c[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = rep ? x_top * cf.ss[k] : 0.0;
+    for (int k = 0; k < K; ++k) c[k] = rep ? xe * cf.ss[k] : 0.0;
     const double pt = cf.pbit[6];  // p^64
-    for (int ty = 0; ty < nty; ++ty) {
-        float *o = base + (int64_t)ty * 2 * K * W;
-        double z[K];
+    for (int i0 = 0; i0 < nty; i0 += U) {
+        double z[U][K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            z[k] = o[(int64_t)k * W];
-            o[(int64_t)k * W] = (float)c[k];
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            const int ty = dir == 0 ? i : nty - 1 - i;
+#pragma unroll
+            for (int k = 0; k < K; ++k) z[u][k] = i < nty ? base[ty * tstride + (int64_t)k * W] : 0.0;
         }
-        cas_advance_add(pt, (double)CT, c, z);
-    }
 #pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = rep ? x_bot * cf.ss[k] : 0.0;
-    for (int ty = nty - 1; ty >= 0; --ty) {
-        float *o = base + (int64_t)ty * 2 * K * W;
-        double z[K];
+        for (int u = 0; u < U; ++u) {
+            const int i = i0 + u;
+            if (i >= nty) break;
+            const int ty = dir == 0 ? i : nty - 1 - i;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            z[k] = o[(int64_t)(K + k) * W];
-            o[(int64_t)(K + k) * W] = (float)c[k];
+            for (int k = 0; k < K; ++k) base[ty * tstride + (int64_t)k * W] = c[k];
+            const int len = min(CT, H - ty * CT);
+            cas_advance_add(len == CT ? pt : pow_bits(cf, len), (double)len, c, z[u]);
         }
-        const int len = min(CT, H - ty * CT);
-        cas_advance_add(len == CT ? pt : pow_bits(cf, len), (double)len, c, z);
     }
 }
 
@@ -434,7 +433,7 @@ __global__ __launch_bounds__(256) void iir_col_scan_kernel(const float *__restri
 template <int K, bool LAP>
 __global__ __launch_bounds__(COL_WPB * 64) void iir_col_final_kernel(
     const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out, int64_t out_pitch,
-    int64_t out_plane_stride, int H, int W, int nty, const float *__restrict__ st, Args a) {
+    int64_t out_plane_stride, int H, int W, int nty, const double *__restrict__ st, Args a) {
     const int lane = threadIdx.x & 63;
     const int ty = blockIdx.y * COL_WPB + (threadIdx.x >> 6);
     const int s = blockIdx.z;
@@ -452,7 +451,7 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_final_kernel(
     for (int j = 0; j < CT; ++j) xs[j] = plane[(int64_t)min(y0 + j, H - 1) * in_pitch];
     double vf[K], vb[K];
     {
-        const float *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + ccol;
+        const double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + ccol;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             vf[k] = o[(int64_t)k * W];
@@ -610,7 +609,7 @@ hipError_t launch_rows_k(const void *in, int64_t H, int64_t W, int64_t in_pitch,
 template <int K>
 hipError_t launch_cols_k(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
                          int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool lap,
-                         const IirParams &prm, float *st, hipStream_t stream) {
+                         const IirParams &prm, double *st, hipStream_t stream) {
     Args a = make_args(prm, 1);
     const int nty = (int)((H + CT - 1) / CT);
     const unsigned S = (unsigned)prm.nscales;
@@ -619,7 +618,7 @@ hipError_t launch_cols_k(const float *in, int64_t in_pitch, int64_t in_plane_str
                        in_plane_stride, (int)H, (int)W, nty, st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g2((unsigned)((W + 255) / 256), S);
+    dim3 g2((unsigned)((W + 255) / 256), S, 2);
     hipLaunchKernelGGL((iir_col_scan_kernel<K>), g2, dim3(256), 0, stream, in, in_pitch, in_plane_stride,
                        (int)H, (int)W, nty, st, a);
     e = hipGetLastError();
@@ -657,13 +656,13 @@ hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int6
 
 size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order) {
     const int64_t nty = (H + CT - 1) / CT;
-    return ((size_t)nscales * nty * 2 * order * W * sizeof(float) + 255) & ~(size_t)255;
+    return ((size_t)nscales * nty * 2 * order * W * sizeof(double) + 255) & ~(size_t)255;
 }
 
 hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
                            int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool laplacian,
                            const IirParams &prm, void *ws, hipStream_t st) {
-    float *states = static_cast<float *>(ws);
+    double *states = static_cast<double *>(ws);
     if (prm.order == 3)
         return launch_cols_k<3>(in, in_pitch, in_plane_stride, out, H, W, pitch, plane_stride, laplacian, prm,
                                 states, st);
