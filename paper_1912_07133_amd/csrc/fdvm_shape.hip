@@ -190,12 +190,12 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
 // popcount totals of SUM_THREADS * SUM_WORDS consecutive words
 __global__ __launch_bounds__(SUM_THREADS) void detect_sums_kernel(const unsigned long long *__restrict__ mask,
                                                                   int64_t nwords, int *__restrict__ bsum) {
+    constexpr int NW = SUM_THREADS * SUM_WORDS;
     __shared__ int part[SUM_THREADS / 64];
-    const int64_t base = ((int64_t)blockIdx.x * SUM_THREADS + threadIdx.x) * SUM_WORDS;
+    const int64_t bbase = (int64_t)blockIdx.x * NW;
     int c = 0;
-#pragma unroll
-    for (int i = 0; i < SUM_WORDS; ++i)
-        if (base + i < nwords) c += __popcll(mask[base + i]);
+    for (int i = threadIdx.x; i < NW; i += SUM_THREADS)  // coalesced
+        if (bbase + i < nwords) c += __popcll(mask[bbase + i]);
     for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o, 64);
     if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
     __syncthreads();
@@ -236,17 +236,20 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
                                                                    const unsigned long long *__restrict__ mask,
                                                                    int64_t nwords, const int *__restrict__ boff,
                                                                    fdvm_blob *__restrict__ out, int cap) {
+    constexpr int NW = SUM_THREADS * SUM_WORDS;
+    __shared__ unsigned long long wbuf[NW];
     __shared__ int part[SUM_THREADS / 64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t base = ((int64_t)blockIdx.x * SUM_THREADS + threadIdx.x) * SUM_WORDS;
-    unsigned long long w[SUM_WORDS];
+    const int64_t bbase = (int64_t)blockIdx.x * NW;
+    // coalesced staging of the block's words
+    for (int i = threadIdx.x; i < NW; i += SUM_THREADS)
+        wbuf[i] = bbase + i < nwords ? mask[bbase + i] : 0ull;
+    __syncthreads();
+    const int first = threadIdx.x * SUM_WORDS;
     int c = 0;
 #pragma unroll
-    for (int i = 0; i < SUM_WORDS; ++i) {
-        w[i] = base + i < nwords ? mask[base + i] : 0ull;
-        c += __popcll(w[i]);
-    }
+    for (int i = 0; i < SUM_WORDS; ++i) c += __popcll(wbuf[first + i]);
     // exclusive prefix of c over the block
     int incl = c;
     for (int o = 1; o < 64; o <<= 1) {
@@ -259,11 +262,10 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
     for (int i = 0; i < wv; ++i) before += part[i];
     int idx = boff[blockIdx.x] + before + incl - c;
     if (c == 0) return;
-#pragma unroll
     for (int i = 0; i < SUM_WORDS; ++i) {
-        unsigned long long bits = w[i];
+        unsigned long long bits = wbuf[first + i];
         if (!bits) continue;
-        const int64_t word = base + i;               // = (s * H + y) * ntx + tx
+        const int64_t word = bbase + first + i;     // = (s * H + y) * ntx + tx
         const int tx = (int)(word % ntx);
         const int64_t sy = word / ntx;
         const int y = (int)(sy % H);

@@ -12,6 +12,15 @@ import numpy as np
 # (normwise per plane; 1e-5 relative in float32).
 RTOL_BLUR = 1e-5
 
+# Laplacian planes V = sigma^2 (D20 + D02): the 5-point stencil has gain 8, so
+# a float32 blur correct to a few units in the last place perturbs V by up to
+# 8 sigma^2 * (a few ulp of max |B|).  Tolerance: 4 ulps (2^-22 relative).
+ULPS_V = 4 * 2.0 ** -24
+
+
+def laplacian_tolerance(sigma, B_ref_plane):
+    return 8.0 * sigma * sigma * ULPS_V * float(np.max(np.abs(B_ref_plane)))
+
 
 def say(*args):
     """Print and flush: names the case before each GPU step."""
@@ -70,8 +79,11 @@ def fragile_mask(V_ref, errs, tau):
     e_s = e[:, None, None]
     lo, hi = neighbour_extremes(V)
     thr = (np.abs(np.abs(V) - tau) <= e_s)
+    # a pixel that fails the threshold by more than e in both results can
+    # never be a detection, whatever its neighbours do
+    cand = np.abs(V) >= tau - e_s
     ext = (np.abs(lo - V) <= 2 * e_nb) | (np.abs(V - hi) <= 2 * e_nb)
-    return thr | ext
+    return thr | (cand & ext)
 
 
 def blob_keys(blobs):
