@@ -233,7 +233,7 @@ def main() -> int:
                   "laplacian_tolerance": "8 sigma^2 * 4 ulp(max|B|) per plane", "detections": int(len(det_gpu)),
                   "oracle_detections": int(len(det_ref)), "fragile_excluded": nfrag,
                   "mismatches_outside_fragile": len(mism),
-                  "ok": bool(vratio <= 1.0 and not mism and nfrag <= 0.01 * V_gpu.size)}
+                  "ok": bool(vratio <= 1.0 and not mism and nfrag <= 0.05 * V_gpu.size)}
         log(f"cpu baseline {cpu['value']} Mpx*scales/s; parity {parity}")
 
     extra_copy = None

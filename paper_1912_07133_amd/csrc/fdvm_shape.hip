@@ -90,7 +90,7 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
                                                                      int ntx) {
     constexpr int RB = DT_ROWS;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tx = blockIdx.x;
     const int x = tx * DT_W - 1 + lane;           // lanes 1..62 are output columns
     const int y0 = (blockIdx.y * DT_WAVES + wv) * RB;
@@ -100,21 +100,22 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     const float qnan = __int_as_float(0x7fc00000);
     // rows y0-1 .. y0+RB of the plane, NaN outside the image
     auto load_plane = [&](int s, float (&v)[RB + 2]) {
-        const float *P = V + (int64_t)s * plane_stride + cx;
+        const float *P = V + (int64_t)s * plane_stride;   // wave-uniform
 #pragma unroll
         for (int r = 0; r < RB + 2; ++r) {
             const int y = y0 - 1 + r;
-            const float t = P[(int64_t)min(max(y, 0), H - 1) * pitch];
+            const float t = P[(int64_t)min(max(y, 0), H - 1) * pitch + cx];
             v[r] = (xin && y >= 0 && y < H) ? t : qnan;
         }
     };
     // separable 3x3 min / max (centre included) for rows y0 .. y0+RB-1, and
     // the 8-neighbour min / max (centre excluded)
-    float cur[RB + 2], nxt[RB + 2];
+    float cur[RB + 2], nxt[RB + 2], pre[RB + 2];
     float m9p[RB], M9p[RB];             // previous plane's 3x3 min / max
     float m9c[RB], M9c[RB], m8c[RB], M8c[RB];
     bool have_prev = false;
     load_plane(0, cur);
+    if (S > 1) load_plane(1, pre);      // raw samples one plane ahead
     auto planes_stats = [&](const float (&v)[RB + 2], float (&m9)[RB], float (&M9)[RB], float (&m8)[RB],
                             float (&M8)[RB]) {
         float rmin[RB + 2], rmax[RB + 2];
@@ -146,7 +147,9 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         float m9n[RB], M9n[RB], m8n[RB], M8n[RB];
         const bool have_next = s + 1 < S;
         if (have_next) {
-            load_plane(s + 1, nxt);
+#pragma unroll
+            for (int r = 0; r < RB + 2; ++r) nxt[r] = pre[r];
+            if (s + 2 < S) load_plane(s + 2, pre);   // in flight while s + 1 is used
             planes_stats(nxt, m9n, M9n, m8n, M8n);
         }
         unsigned long long *mrow = mask + ((int64_t)s * H + y0) * ntx + tx;
@@ -265,11 +268,11 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
     for (int i = 0; i < SUM_WORDS; ++i) {
         unsigned long long bits = wbuf[first + i];
         if (!bits) continue;
-        const int64_t word = bbase + first + i;     // = (s * H + y) * ntx + tx
-        const int tx = (int)(word % ntx);
-        const int64_t sy = word / ntx;
-        const int y = (int)(sy % H);
-        const int s = (int)(sy / H);
+        const unsigned word = (unsigned)(bbase + first + i);  // = (s * H + y) * ntx + tx
+        const unsigned sy = word / (unsigned)ntx;
+        const int tx = (int)(word - sy * (unsigned)ntx);
+        const int s = (int)(sy / (unsigned)H);
+        const int y = (int)(sy - (unsigned)s * (unsigned)H);
         while (bits) {
             const int b = __ffsll((long long)bits) - 1;
             bits &= bits - 1;
