@@ -83,14 +83,14 @@ def main() -> int:
     torch.cuda.synchronize()
     h2d_ms = (time.perf_counter() - t0) * 1e3
 
-    R = torch.empty((S, H, W), dtype=torch.float32, device=dev)   # x-pass planes
     V = torch.empty((S, H, W), dtype=torch.float32, device=dev)   # sigma^2 (D20 + D02)
     B = torch.empty((S, H, W), dtype=torch.float32, device=dev)   # FIR blur planes
     cap = 1 << 20
     blobs = torch.empty(cap * P.BLOB_BYTES, dtype=torch.uint8, device=dev)
     count = torch.zeros(1, dtype=torch.int32, device=dev)
     ws_det = torch.empty(P.workspace_bytes(P.OP_DETECT, H, W, S), dtype=torch.uint8, device=dev)
-    ws_iir = torch.empty(P.workspace_bytes(P.OP_BLUR_IIR, H, W, S), dtype=torch.uint8, device=dev)
+    # x-pass intermediate (S fixed-point planes), column states, row exponents
+    ws_iir = torch.empty(P.workspace_bytes(P.OP_IIR_LAPLACIAN, H, W, S), dtype=torch.uint8, device=dev)
     sigmas_c = (ctypes.c_double * S)(*sig)
     stream = torch.cuda.current_stream(dev)
     sp = int(stream.cuda_stream)
@@ -113,13 +113,10 @@ def main() -> int:
     def iir_step(ev):
         filt = designs()
         ev[0].record(stream)
-        check(L.fdvm_iir_pass(x.data_ptr(), P.U16, H, W, W, 0, R.data_ptr(), W, H * W, filt, S,
-                              P.BC_REPLICATE, 0, None, 0, sp), "rows")
+        check(L.fdvm_iir_laplacian(x.data_ptr(), P.U16, H, W, W, V.data_ptr(), W, H * W, filt, S,
+                                   P.BC_REPLICATE, ws_iir.data_ptr(), ws_iir.numel(), sp), "iir_laplacian")
         ev[1].record(stream)
-        check(L.fdvm_iir_pass(R.data_ptr(), P.F32, H, W, W, H * W, V.data_ptr(), W, H * W, filt, S,
-                              P.BC_REPLICATE, 2, ws_iir.data_ptr(), ws_iir.numel(), sp), "cols+laplacian")
-        ev[2].record(stream)
-        detect_into(ev[3])
+        detect_into(ev[2])
 
     def timed(step_fn, nev, steps, warmup):
         for _ in range(warmup):
@@ -141,22 +138,22 @@ def main() -> int:
 
     # ---------------- IIR path
     log(f"IIR: {H}x{W} u16, {S} scales, warmup {args.warmup}, steps {args.steps}")
-    total_ms, wall, per = timed(iir_step, 4, args.steps, args.warmup)
+    total_ms, wall, per = timed(iir_step, 3, args.steps, args.warmup)
     ms_step = total_ms / args.steps
     n_det = int(count.item())
     mpx = H * W * S / 1e6
     value = mpx / (ms_step / 1e3)
-    # algorithmic bytes per launch: the x pass reads the frame once for all
-    # scales and writes S planes; the y pass + Laplacian reads S planes and
-    # writes S planes; detection reads S planes
+    # algorithmic bytes per call (two-pass schedule): the x pass reads the
+    # frame once for all scales and writes S intermediate planes (4 B/px); the
+    # y pass with the fused Laplacian reads them and writes S planes of V;
+    # detection reads the S planes of V once
     kern = {
-        "iir_rows": {"ms": per[0], "bytes": H * W * (2 + 4 * S), "kernels": 1},
-        "iir_cols_laplacian": {"ms": per[1], "bytes": H * W * S * 8, "kernels": 3},
-        "detect": {"ms": per[2], "bytes": H * W * S * 4, "kernels": 3},
+        "iir_laplacian": {"ms": per[0], "bytes": H * W * (2 + 12 * S), "kernels": 4},
+        "detect": {"ms": per[1], "bytes": H * W * S * 4, "kernels": 4},
     }
     for k in kern.values():
         k["GB/s"] = k["bytes"] / (k["ms"] / 1e3) / 1e9
-    dominant = max(["iir_rows", "iir_cols_laplacian", "detect"], key=lambda k: kern[k]["ms"])
+    dominant = max(kern, key=lambda k: kern[k]["ms"])
     d = kern[dominant]
     traffic = None
     if os.path.exists(PMC_FILE):

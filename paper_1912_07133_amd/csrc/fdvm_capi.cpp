@@ -99,10 +99,10 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
 size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len) {
     if (H < 1 || W < 1 || nscales < 1) return 0;
     switch (op) {
-        case FDVM_OP_BLUR_IIR: return iir_cols_workspace_bytes(H, W, nscales, 3);
+        case FDVM_OP_BLUR_IIR: return iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H);
         case FDVM_OP_IIR_LAPLACIAN:
-            return (((size_t)H * W * sizeof(float) + 255) & ~(size_t)255) * nscales +
-                   iir_cols_workspace_bytes(H, W, nscales, 3);
+            return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
+                   iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H);
         case FDVM_OP_BLUR_FIR: return fir_workspace_bytes(H, W, nscales, max_half_len);
         case FDVM_OP_DETECT: return detect_workspace_bytes(H, W, nscales);
         default: return 0;
@@ -157,7 +157,7 @@ fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     hipStream_t hs = static_cast<hipStream_t>(stream);
     if (axis == 0) {
         if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
-        return from_hip(launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs));
+        return from_hip(launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, nullptr, prm, hs));
     }
     if (axis == 1 || axis == 2) {
         if (dt != FDVM_F32) return FDVM_EINVAL;
@@ -167,8 +167,8 @@ fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
             return FDVM_EINVAL;
         if (!ws) return FDVM_EINVAL;
         if (ws_bytes < iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;
-        return from_hip(launch_iir_cols(static_cast<const float *>(in), in_pitch, in_plane_stride, out, H, W,
-                                        out_pitch, plane_stride, axis == 2, prm, ws, hs));
+        return from_hip(launch_iir_cols(in, in_pitch, in_plane_stride, nullptr, out, H, W, out_pitch, plane_stride,
+                                        axis == 2, prm, ws, hs));
     }
     return FDVM_EINVAL;
 }
@@ -186,13 +186,16 @@ fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     st = iir_params(filters, nscales, bc, &prm);
     if (st != FDVM_OK) return st;
     if (!ws) return FDVM_EINVAL;
-    if (ws_bytes < iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;
+    const size_t st_bytes = iir_cols_workspace_bytes(H, W, nscales, prm.order);
+    if (ws_bytes < st_bytes + iir_rexp_bytes(H)) return FDVM_ENOMEM;
     if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, prm, hs);
+    // the fixed-point intermediate lives in `out` and is replaced in place
+    int *rexp = reinterpret_cast<int *>(static_cast<char *>(ws) + st_bytes);
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, hs);
     if (e != hipSuccess) return FDVM_EDEVICE;
-    return from_hip(launch_iir_cols(out, out_pitch, plane_stride, out, H, W, out_pitch, plane_stride, false, prm,
-                                    ws, hs));
+    return from_hip(launch_iir_cols(out, out_pitch, plane_stride, rexp, out, H, W, out_pitch, plane_stride, false,
+                                    prm, ws, hs));
 }
 
 fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
@@ -207,17 +210,21 @@ fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
     st = iir_params(filters, nscales, bc, &prm);
     if (st != FDVM_OK) return st;
     if (!ws) return FDVM_EINVAL;
-    const size_t plane_bytes = ((size_t)H * W * sizeof(float) + 255) & ~(size_t)255;
-    const size_t need = plane_bytes * nscales + iir_cols_workspace_bytes(H, W, nscales, prm.order);
+    const size_t plane_bytes = ((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t st_bytes = iir_cols_workspace_bytes(H, W, nscales, prm.order);
+    const size_t need = plane_bytes * nscales + st_bytes + iir_rexp_bytes(H);
     if (ws_bytes < need) return FDVM_ENOMEM;
     if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
     hipStream_t hs = static_cast<hipStream_t>(stream);
-    float *rows = static_cast<float *>(ws);                       // x-pass planes, pitch W
-    const int64_t rstride = (int64_t)(plane_bytes / sizeof(float));
+    // ws: x-pass fixed-point planes (pitch W) | column states | row exponents
+    int32_t *rows = static_cast<int32_t *>(ws);
+    const int64_t rstride = (int64_t)(plane_bytes / sizeof(int32_t));
     void *states = static_cast<char *>(ws) + plane_bytes * nscales;
-    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, rows, W, rstride, prm, hs);
+    int *rexp = reinterpret_cast<int *>(static_cast<char *>(states) + st_bytes);
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, rows, W, rstride, rexp, prm, hs);
     if (e != hipSuccess) return FDVM_EDEVICE;
-    return from_hip(launch_iir_cols(rows, W, rstride, out, H, W, out_pitch, plane_stride, true, prm, states, hs));
+    return from_hip(
+        launch_iir_cols(rows, W, rstride, rexp, out, H, W, out_pitch, plane_stride, true, prm, states, hs));
 }
 
 fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,

@@ -13,6 +13,15 @@
 // Laplacian (gain ~8 sigma^2) would otherwise amplify.  Planes are stored as
 // float32.
 //
+// The x-pass intermediate between the two passes is either float32 planes
+// (the public two-pass API) or, on the fused routes, int32 fixed point with one
+// binary exponent per image row: q = rint(r 2^e_y), e_y chosen from the row's
+// input maximum and an upper bound on the blur's l1 norm so that |q| < 2^31.
+// Its absolute resolution is 32-64 times finer than float32 at the frame's
+// full-scale value for the same 4 bytes per sample; that matters because the
+// x-pass rounding is white along x and the scale-normalised second difference
+// along x multiplies it by ~8 sigma^2.
+//
 // The zero-input transition over n samples is
 //     A^n = p^n [[1,0,0],[n,1,0],[n(n+1)/2,n,1]]
 // (K = 3; the upper-left block for K = 2), so a line cut into chunks is the
@@ -60,8 +69,45 @@ struct Args {
     int nscales;
     int boundary;
     int pad0, pad1;
+    double l1;  // upper bound on the l1 norm of every scale's 1-D blur
     ScaleArgs s[FDVM_MAX_SCALES];
 };
+
+// the x-pass intermediate: float32 planes, or int32 fixed point with the
+// per-row exponents rexp (sample = q 2^-rexp[y])
+template <bool FX>
+struct Mid {
+    const void *base;
+    int64_t pitch, pstride;
+    const int *rexp;
+    __device__ __forceinline__ double at(int s, int y, int x) const {
+        return cvt(raw(s, y, x), row_scale(y));
+    }
+    __device__ __forceinline__ uint32_t raw(int s, int y, int x) const {
+        const int64_t o = (int64_t)s * pstride + (int64_t)y * pitch + x;
+        return static_cast<const uint32_t *>(base)[o];
+    }
+    // 2^-rexp[y] (1 for float planes)
+    __device__ __forceinline__ double row_scale(int y) const {
+        if constexpr (FX)
+            return ldexp(1.0, -rexp[y]);
+        else
+            return 1.0;
+    }
+    __device__ __forceinline__ double cvt(uint32_t r, double scale) const {
+        if constexpr (FX)
+            return (double)(int)r * scale;
+        else
+            return (double)__uint_as_float(r);
+    }
+};
+
+// lane l's value of a float64, as a wave-uniform value
+__device__ __forceinline__ double read_lane_d(double v, int l) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+    return __hiloint2double(hi, lo);
+}
 
 // ------------------------------------------------------------ recursion
 template <int K>
@@ -142,13 +188,15 @@ __device__ __forceinline__ float load_as_float<bf16_t>(const bf16_t *p) {
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 // ------------------------------------------------------------ row pass
-template <int K, int C, int R, typename TIn>
+template <int K, int C, int R, typename TIn, bool FX>
 __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
-    const TIn *__restrict__ in, int64_t in_pitch, float *__restrict__ out, int64_t out_pitch,
-    int64_t plane_stride, int H, int W, Args a) {
+    const TIn *__restrict__ in, int64_t in_pitch, void *__restrict__ out_v, int64_t out_pitch,
+    int64_t plane_stride, int H, int W, int *__restrict__ rexp, Args a) {
+    using Acc = std::conditional_t<FX, double, float>;
     constexpr int LP = C + 1;  // padded lane stride in LDS: conflict-free chunk reads
     __shared__ float buf[ROW_WPB][64 * LP];
     __shared__ double tot[ROW_WPB][2][K];
+    __shared__ float rmax[ROW_WPB];
 
     const int lane = threadIdx.x & 63;
     const int wv = wave_id();
@@ -166,16 +214,34 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 
     // stage the wavefront's part of the row: element j of the segment goes to
     // lds[j + j / C] (lane j / C, position j % C)
+    float amax = 0.0f;
 #pragma unroll 4
     for (int i = 0; i < C; ++i) {
         const int j = i * 64 + lane;
         const int col = seg0 + j;
         const float v = load_as_float(src + min(col, W - 1));
-        lds[j + j / C] = (row_ok && col < W) ? v : 0.0f;
+        const float t = (row_ok && col < W) ? v : 0.0f;
+        lds[j + j / C] = t;
+        amax = fmaxf(amax, fabsf(t));
     }
     const double x_first = load_as_float(src);
     const double x_last = load_as_float(src + (W - 1));
+    if constexpr (FX) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
+        if (lane == 0) rmax[wv] = amax;
+    }
     __syncthreads();
+    // fixed-point exponent of this row: |out| <= max|x| * l1 < 2^(ilogb + 1)
+    int ex = 0;
+    if constexpr (FX) {
+        float m = 0.0f;
+#pragma unroll
+        for (int q = 0; q < R; ++q) m = fmaxf(m, rmax[wv - r + q]);
+        const double bound = (double)m * a.l1;
+        ex = bound > 0.0 ? 30 - ilogb(bound) : 0;
+        if (row_ok && r == 0 && lane == 0) rexp[row] = ex;
+    }
     float xs[C];
 #pragma unroll
     for (int j = 0; j < C; ++j) xs[j] = lds[lane * LP + j];
@@ -303,46 +369,55 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         // ---- final outputs of the chunk
         // y-(n) + b0 x(n) is kept as float32 until y+(n) is added in float64
         // (its rounding adds ~1/4 ulp to the 1/2 ulp of the stored output)
-        float ys[C];
+        // (float64 throughout for the fixed-point intermediate)
+        Acc ys[C];
         if (full_wave) {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
-                ys[j] = (float)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
                 cas_step(p, vb, (double)xs[j]);
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                ys[j] = (float)((double)ys[j] + cas_out(cf, vf));
+                ys[j] = (Acc)((double)ys[j] + cas_out(cf, vf));
                 cas_step(p, vf, (double)xs[j]);
             }
         } else {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
                 if (j < nv) {
-                    ys[j] = (float)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
+                    ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
                     cas_step(p, vb, (double)xs[j]);
                 } else {
-                    ys[j] = 0.0f;
+                    ys[j] = (Acc)0;
                 }
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 if (j < nv) {
-                    ys[j] = (float)((double)ys[j] + cas_out(cf, vf));
+                    ys[j] = (Acc)((double)ys[j] + cas_out(cf, vf));
                     cas_step(p, vf, (double)xs[j]);
                 }
             }
         }
-        // ---- back through LDS to coalesced stores
+        // ---- back through LDS (as raw 32-bit words) to coalesced stores
 #pragma unroll
-        for (int j = 0; j < C; ++j) lds[lane * LP + j] = ys[j];
+        for (int j = 0; j < C; ++j) {
+            if constexpr (FX) {
+                const double q = fmin(fmax(rint(ldexp(ys[j], ex)), -2147483648.0), 2147483647.0);
+                lds[lane * LP + j] = __int_as_float((int)q);
+            } else {
+                lds[lane * LP + j] = ys[j];
+            }
+        }
         __syncthreads();
-        float *dst = out + (int64_t)s * plane_stride + (int64_t)(row_ok ? row : 0) * out_pitch;
+        uint32_t *dst = static_cast<uint32_t *>(out_v) + (int64_t)s * plane_stride +
+                        (int64_t)(row_ok ? row : 0) * out_pitch;
 #pragma unroll 4
         for (int i = 0; i < C; ++i) {
             const int j = i * 64 + lane;
             const int col = seg0 + j;
-            if (row_ok && col < W) dst[col] = lds[j + j / C];
+            if (row_ok && col < W) dst[col] = __float_as_uint(lds[j + j / C]);
         }
         __syncthreads();
     }
@@ -351,10 +426,9 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 // ------------------------------------------------------------ column pass
 // (a) zero-state end states of every 64-row tile (float64).  st layout:
 //     st[((s * nty + ty) * 2K + k) * W + x], k < K forward, k >= K backward.
-template <int K>
-__global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
-    const float *__restrict__ in, int64_t pitch, int64_t plane_stride, int H, int W, int nty,
-    double *__restrict__ st, Args a) {
+template <int K, bool FX>
+__global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m, int H, int W, int nty,
+                                                                      double *__restrict__ st, Args a) {
     const int lane = threadIdx.x & 63;
     const int ty = blockIdx.y * COL_WPB + wave_id();
     const int s = blockIdx.z;
@@ -364,21 +438,22 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
     const ScaleArgs &cf = a.s[s];
     const double p = cf.p;
     const int y0 = ty * CT;
-    const float *plane = in + (int64_t)s * plane_stride;   // wave-uniform
-    float xs[CT];
+    static_assert(CT == 64, "one row scale per lane");
+    const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
+    uint32_t xs[CT];
 #pragma unroll
     for (int j = 0; j < CT; ++j) {
         const int y = y0 + j;
-        const float v = plane[(int64_t)min(y, H - 1) * pitch + ccol];
-        xs[j] = y < H ? v : 0.0f;  // zeros after the last row leave the
-    }                              // backward zero state exact
+        const uint32_t v = m.raw(s, min(y, H - 1), ccol);
+        xs[j] = y < H ? v : 0u;  // zeros (in either format) after the last row
+    }                            // leave the backward zero state exact
     double zf[K], zb[K];
     set_zero(zf);
     set_zero(zb);
 #pragma unroll
-    for (int j = 0; j < CT; ++j) cas_step(p, zf, (double)xs[j]);
+    for (int j = 0; j < CT; ++j) cas_step(p, zf, m.cvt(xs[j], read_lane_d(lsc, j)));
 #pragma unroll
-    for (int j = CT - 1; j >= 0; --j) cas_step(p, zb, (double)xs[j]);
+    for (int j = CT - 1; j >= 0; --j) cas_step(p, zb, m.cvt(xs[j], read_lane_d(lsc, j)));
     if (col < W) {
         double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + col;
 #pragma unroll
@@ -392,9 +467,8 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(
 // (b) carries: in place, every tile's forward zero state becomes the forward
 // state entering the tile from above, every backward zero state the backward
 // state entering it from below.
-template <int K>
-__global__ __launch_bounds__(256) void iir_col_scan_kernel(const float *__restrict__ in, int64_t pitch,
-                                                           int64_t plane_stride, int H, int W, int nty,
+template <int K, bool FX>
+__global__ __launch_bounds__(256) void iir_col_scan_kernel(Mid<FX> m, int H, int W, int nty,
                                                            double *__restrict__ st, Args a) {
     constexpr int U = 4;  // tiles whose states are fetched together
     const int col = blockIdx.x * 256 + threadIdx.x;
@@ -402,9 +476,8 @@ __global__ __launch_bounds__(256) void iir_col_scan_kernel(const float *__restri
     const int dir = blockIdx.z;  // 0: forward from the top, 1: backward from the bottom
     if (col >= W) return;
     const ScaleArgs &cf = a.s[s];
-    const float *plane = in + (int64_t)s * plane_stride + col;
     const bool rep = a.boundary == FDVM_BC_REPLICATE;
-    const double xe = dir == 0 ? (double)plane[0] : (double)plane[(int64_t)(H - 1) * pitch];
+    const double xe = m.at(s, dir == 0 ? 0 : H - 1, col);
     double *base = st + (int64_t)s * nty * 2 * K * W + (int64_t)dir * K * W + col;
     const int64_t tstride = (int64_t)2 * K * W;
     double c[K];
@@ -456,10 +529,10 @@ __device__ __forceinline__ double lane_right_d(double v) {
 // the state entering each quarter from below; then every quarter, top first,
 // is swept backwards from its recorded state and finished by the forward
 // sweep, which runs through the whole tile.
-template <int K, bool LAP>
+template <int K, bool LAP, bool FX>
 __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 8))) void iir_col_final_kernel(
-    const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out, int64_t out_pitch,
-    int64_t out_plane_stride, int H, int W, int nty, const double *__restrict__ st, Args a) {
+    Mid<FX> m, float *out, int64_t out_pitch, int64_t out_plane_stride, int H, int W, int nty,
+    const double *__restrict__ st, Args a) {
     constexpr int QT = 16;
     constexpr int NQ = CT / QT;
     const int lane = threadIdx.x & 63;
@@ -473,8 +546,8 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
     const int y0 = ty * CT;
     const int y1 = min(y0 + CT, H);
     const int len = y1 - y0;
-    const float *pin = in + (int64_t)s * in_plane_stride;      // wave-uniform
-    auto xin = [&](int y) { return pin[(int64_t)y * in_pitch + ccol]; };
+    auto xin = [&](int y) { return m.at(s, y, ccol); };
+    const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
     double vf[K], ub[NQ][K];
     {
         const double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + ccol;
@@ -506,7 +579,8 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
         double bm = 0.0, bc = 0.0;  // sliding B(n-1), B(n) for the Laplacian
         auto load_q = [&](int q) {
 #pragma unroll
-            for (int i = 0; i < QT; ++i) xd[i] = (double)xin(min(y0 + q * QT + i, H - 1));
+            for (int i = 0; i < QT; ++i)
+                xd[i] = m.cvt(m.raw(s, min(y0 + q * QT + i, H - 1), ccol), read_lane_d(lsc, q * QT + i));
         };
         auto emit = [&](int y, double bmv, double bcv, double bnv) {
             const double bl = lane_left_d(bcv);
@@ -587,10 +661,25 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
         body(std::false_type{});
 }
 
+// Upper bound on sum_n |h(n)| of the two-sided blur: the impulse response of
+// every cascade section v_k is non-negative with sum ss[k] = 1/(1-p)^k, so
+// sum |h| <= |b0| + 2 sum_k |w_k| ss[k].  Slightly enlarged against rounding.
+double l1_bound(const IirParams &prm) {
+    double m = 0.0;
+    for (int s = 0; s < prm.nscales; ++s) {
+        const IirScaleParams &q = prm.s[s];
+        double b = std::fabs(q.b0);
+        for (int k = 0; k < prm.order; ++k) b += 2.0 * std::fabs(q.w[k]) * q.ss[k];
+        m = std::fmax(m, b);
+    }
+    return m * (1.0 + 1e-9);
+}
+
 Args make_args(const IirParams &prm, int C) {
     Args a{};
     a.nscales = prm.nscales;
     a.boundary = prm.boundary;
+    a.l1 = l1_bound(prm);
     for (int s = 0; s < prm.nscales; ++s) {
         const IirScaleParams &q = prm.s[s];
         ScaleArgs &d = a.s[s];
@@ -611,72 +700,93 @@ Args make_args(const IirParams &prm, int C) {
 }
 
 template <int K, int C, int R, typename T>
-hipError_t launch_rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, float *out,
-                         int64_t out_pitch, int64_t plane_stride, const IirParams &prm, hipStream_t st) {
+hipError_t launch_rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, void *out, int64_t out_pitch,
+                         int64_t plane_stride, int *rexp, const IirParams &prm, hipStream_t st) {
     Args a = make_args(prm, C);
     const int rows_per_block = ROW_WPB / R;
     dim3 grid((unsigned)((H + rows_per_block - 1) / rows_per_block));
-    hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T>), grid, dim3(ROW_WPB * 64), 0, st,
-                       static_cast<const T *>(in), in_pitch, out, out_pitch, plane_stride, (int)H,
-                       (int)W, a);
+    if (rexp)
+        hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T, true>), grid, dim3(ROW_WPB * 64), 0, st,
+                           static_cast<const T *>(in), in_pitch, out, out_pitch, plane_stride, (int)H, (int)W,
+                           rexp, a);
+    else
+        hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T, false>), grid, dim3(ROW_WPB * 64), 0, st,
+                           static_cast<const T *>(in), in_pitch, out, out_pitch, plane_stride, (int)H, (int)W,
+                           rexp, a);
     return hipGetLastError();
 }
 
 template <int K, typename T>
-hipError_t launch_rows_k(const void *in, int64_t H, int64_t W, int64_t in_pitch, float *out,
-                         int64_t out_pitch, int64_t plane_stride, const IirParams &prm, hipStream_t st) {
+hipError_t launch_rows_k(const void *in, int64_t H, int64_t W, int64_t in_pitch, void *out, int64_t out_pitch,
+                         int64_t plane_stride, int *rexp, const IirParams &prm, hipStream_t st) {
     // chunk length C per lane and wavefronts per row R: smallest C in
     // {8, 16, 32} with 64 C R >= W, R in {1, 2, 4, 8}
-    if (W <= 64 * 8) return launch_rows_t<K, 8, 1, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
-    if (W <= 64 * 16) return launch_rows_t<K, 16, 1, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
-    if (W <= 64 * 32) return launch_rows_t<K, 32, 1, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
-    if (W <= 2 * 64 * 32) return launch_rows_t<K, 32, 2, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
-    if (W <= 4 * 64 * 32) return launch_rows_t<K, 32, 4, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
-    if (W <= 8 * 64 * 32) return launch_rows_t<K, 32, 8, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
+#define FDVM_ROWS_CR(CC, RR) \
+    return launch_rows_t<K, CC, RR, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st)
+    if (W <= 64 * 8) FDVM_ROWS_CR(8, 1);
+    if (W <= 64 * 16) FDVM_ROWS_CR(16, 1);
+    if (W <= 64 * 32) FDVM_ROWS_CR(32, 1);
+    if (W <= 2 * 64 * 32) FDVM_ROWS_CR(32, 2);
+    if (W <= 4 * 64 * 32) FDVM_ROWS_CR(32, 4);
+    if (W <= 8 * 64 * 32) FDVM_ROWS_CR(32, 8);
+#undef FDVM_ROWS_CR
     return hipErrorInvalidValue;
 }
 
-template <int K>
-hipError_t launch_cols_k(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
-                         int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool lap,
-                         const IirParams &prm, double *st, hipStream_t stream) {
+template <int K, bool FX>
+hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                          bool lap, const IirParams &prm, double *st, hipStream_t stream) {
     Args a = make_args(prm, 1);
     const int nty = (int)((H + CT - 1) / CT);
     const unsigned S = (unsigned)prm.nscales;
     dim3 g1((unsigned)((W + 63) / 64), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
-    hipLaunchKernelGGL((iir_col_states_kernel<K>), g1, dim3(COL_WPB * 64), 0, stream, in, in_pitch,
-                       in_plane_stride, (int)H, (int)W, nty, st, a);
+    hipLaunchKernelGGL((iir_col_states_kernel<K, FX>), g1, dim3(COL_WPB * 64), 0, stream, m, (int)H, (int)W, nty,
+                       st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2((unsigned)((W + 255) / 256), S, 2);
-    hipLaunchKernelGGL((iir_col_scan_kernel<K>), g2, dim3(256), 0, stream, in, in_pitch, in_plane_stride,
-                       (int)H, (int)W, nty, st, a);
+    hipLaunchKernelGGL((iir_col_scan_kernel<K, FX>), g2, dim3(256), 0, stream, m, (int)H, (int)W, nty, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (lap) {
         dim3 g3((unsigned)((W + 61) / 62), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
-        hipLaunchKernelGGL((iir_col_final_kernel<K, true>), g3, dim3(COL_WPB * 64), 0, stream, in, in_pitch,
-                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, nty, st, a);
+        hipLaunchKernelGGL((iir_col_final_kernel<K, true, FX>), g3, dim3(COL_WPB * 64), 0, stream, m, out, pitch,
+                           plane_stride, (int)H, (int)W, nty, st, a);
     } else {
         dim3 g3((unsigned)((W + 63) / 64), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
-        hipLaunchKernelGGL((iir_col_final_kernel<K, false>), g3, dim3(COL_WPB * 64), 0, stream, in, in_pitch,
-                           in_plane_stride, out, pitch, plane_stride, (int)H, (int)W, nty, st, a);
+        hipLaunchKernelGGL((iir_col_final_kernel<K, false, FX>), g3, dim3(COL_WPB * 64), 0, stream, m, out, pitch,
+                           plane_stride, (int)H, (int)W, nty, st, a);
     }
     return hipGetLastError();
 }
 
+template <int K>
+hipError_t launch_cols_k(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp, float *out,
+                         int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool lap,
+                         const IirParams &prm, double *st, hipStream_t stream) {
+    if (rexp)
+        return launch_cols_kx<K, true>(Mid<true>{in, in_pitch, in_plane_stride, rexp}, out, H, W, pitch,
+                                       plane_stride, lap, prm, st, stream);
+    return launch_cols_kx<K, false>(Mid<false>{in, in_pitch, in_plane_stride, nullptr}, out, H, W, pitch,
+                                    plane_stride, lap, prm, st, stream);
+}
+
 }  // namespace
 
-hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
-                           float *out, int64_t out_pitch, int64_t plane_stride,
-                           const IirParams &prm, hipStream_t st) {
-#define FDVM_ROWS_DT(KK)                                                                                     \
-    switch (dtype) {                                                                                         \
-        case FDVM_U16: return launch_rows_k<KK, uint16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st); \
-        case FDVM_F32: return launch_rows_k<KK, float>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);    \
-        case FDVM_F16: return launch_rows_k<KK, _Float16>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st); \
-        case FDVM_BF16: return launch_rows_k<KK, bf16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);  \
-        default: return hipErrorInvalidValue;                                                                \
+hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, void *out,
+                           int64_t out_pitch, int64_t plane_stride, int *rexp, const IirParams &prm,
+                           hipStream_t st) {
+#define FDVM_ROWS_DT(KK)                                                                                    \
+    switch (dtype) {                                                                                        \
+        case FDVM_U16:                                                                                      \
+            return launch_rows_k<KK, uint16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st); \
+        case FDVM_F32:                                                                                      \
+            return launch_rows_k<KK, float>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st);    \
+        case FDVM_F16:                                                                                      \
+            return launch_rows_k<KK, _Float16>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st); \
+        case FDVM_BF16:                                                                                     \
+            return launch_rows_k<KK, bf16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st);   \
+        default: return hipErrorInvalidValue;                                                               \
     }
     if (prm.order == 3) { FDVM_ROWS_DT(3) }
     if (prm.order == 2) { FDVM_ROWS_DT(2) }
@@ -689,16 +799,16 @@ size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order) {
     return ((size_t)nscales * nty * 2 * order * W * sizeof(double) + 255) & ~(size_t)255;
 }
 
-hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
+hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp, float *out,
                            int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool laplacian,
                            const IirParams &prm, void *ws, hipStream_t st) {
     double *states = static_cast<double *>(ws);
     if (prm.order == 3)
-        return launch_cols_k<3>(in, in_pitch, in_plane_stride, out, H, W, pitch, plane_stride, laplacian, prm,
-                                states, st);
+        return launch_cols_k<3>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, laplacian,
+                                prm, states, st);
     if (prm.order == 2)
-        return launch_cols_k<2>(in, in_pitch, in_plane_stride, out, H, W, pitch, plane_stride, laplacian, prm,
-                                states, st);
+        return launch_cols_k<2>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, laplacian,
+                                prm, states, st);
     return hipErrorInvalidValue;
 }
 

@@ -51,13 +51,18 @@ struct IirParams {
     IirScaleParams s[FDVM_MAX_SCALES];
 };
 
+// Row pass.  rexp == nullptr: `out` receives float32 planes.  Otherwise `out`
+// receives the int32 fixed-point intermediate and rexp[y] the exponent of row y
+// (sample = q 2^-rexp[y]).
 hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
-                           float *out, int64_t out_pitch, int64_t plane_stride,
+                           void *out, int64_t out_pitch, int64_t plane_stride, int *rexp,
                            const IirParams &prm, hipStream_t stream);
 size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order);
-hipError_t launch_iir_cols(const float *in, int64_t in_pitch, int64_t in_plane_stride, float *out,
-                           int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool laplacian,
-                           const IirParams &prm, void *ws, hipStream_t stream);
+inline size_t iir_rexp_bytes(int64_t H) { return ((size_t)H * sizeof(int) + 255) & ~(size_t)255; }
+// Column pass over either intermediate format (rexp as for launch_iir_rows).
+hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp,
+                           float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                           bool laplacian, const IirParams &prm, void *ws, hipStream_t stream);
 
 hipError_t launch_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                            int nscales, const float *norms, unsigned what,

@@ -27,7 +27,7 @@ constexpr int DT_W = 62;          // output columns per detection tile
 constexpr int DT_ROWS = 8;        // rows per wavefront
 constexpr int DT_WAVES = 4;       // wavefronts per work-group
 constexpr int SUM_THREADS = 256;
-constexpr int SUM_WORDS = 16;     // words per thread in sums / emit
+constexpr int SUM_WORDS = 4;      // words per thread in sums / emit
 constexpr int SCAN_BLOCK = 1024;
 
 struct Norms {

@@ -153,18 +153,27 @@ def test_fused_laplacian_full_frame():
     got = P.iir_laplacian(x, cfg["sigmas"], order=3).cpu().numpy()
     res = check_v(got, x64, cfg["sigmas"], 3, "replicate")
     say("   V error / tolerance " + " ".join("%.2g/%.2g" % r for r in res))
+    # the fixed-point intermediate keeps the fused V two orders of magnitude
+    # inside the tolerance of a Laplacian taken from float32 blur planes
+    # (measured: error / tolerance ~1e-3 at every scale)
+    assert all(err <= tol / 100 for err, tol in res)
 
 
 def test_pass_api_matches_blur():
-    say("case: iir_pass axis 0 + axis 1 == blur_iir; axis 2 == iir_laplacian")
+    """The two-pass API (float32 intermediate) against the one-call routes
+    (fixed-point intermediate) and the oracle; in-place axis 1 is exact."""
+    say("case: iir_pass axis 0 + axis 1 ~ blur_iir; axis 2 ~ iir_laplacian")
     frame = syn.aerial_frame(300, 500, 4)
-    x, _ = to_dev(frame, "u16")
+    x, x64 = to_dev(frame, "u16")
     sig = [1.0, 5.0, 30.0]
     rows = P.iir_pass(x, sig, axis=0)
     B = P.iir_pass(rows, sig, axis=1)
-    assert torch.equal(B, P.blur_iir(x, sig))
+    ref = oracle_bank(x64, sig, 3, "replicate")
+    assert_planes_close(B.cpu().numpy(), ref)
+    assert_planes_close(P.blur_iir(x, sig).cpu().numpy(), ref)
     rows2 = P.iir_pass(x, sig, axis=0)
     P.iir_pass(rows2, sig, axis=1, out=rows2)        # in place
     assert torch.equal(rows2, B)
-    V = P.iir_pass(P.iir_pass(x, sig, axis=0), sig, axis=2)
-    assert torch.equal(V, P.iir_laplacian(x, sig))
+    V = P.iir_pass(P.iir_pass(x, sig, axis=0), sig, axis=2).cpu().numpy()
+    check_v(V, x64, sig, 3, "replicate", "two-pass")
+    check_v(P.iir_laplacian(x, sig).cpu().numpy(), x64, sig, 3, "replicate", "fused")
