@@ -239,7 +239,7 @@ def main() -> int:
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         for _ in range(3):
-            dst.copy_(src)
+            torch.mul(src, 1.0, out=dst)   # elementwise: reads 256 MiB, writes 256 MiB
         torch.cuda.synchronize()
         extra_copy = {"bytes_each_way": src.numel() * 4}
 

@@ -83,6 +83,9 @@ struct Mid {
     __device__ __forceinline__ double at(int s, int y, int x) const {
         return cvt(raw(s, y, x), row_scale(y));
     }
+    __device__ __forceinline__ const uint32_t *ptr(int s, int y, int x) const {
+        return static_cast<const uint32_t *>(base) + (int64_t)s * pstride + (int64_t)y * pitch + x;
+    }
     __device__ __forceinline__ uint32_t raw(int s, int y, int x) const {
         const int64_t o = (int64_t)s * pstride + (int64_t)y * pitch + x;
         return static_cast<const uint32_t *>(base)[o];
@@ -183,6 +186,14 @@ __device__ __forceinline__ float load_as_float<bf16_t>(const bf16_t *p) {
     return __uint_as_float(((uint32_t)p->bits) << 16);
 }
 
+// Orders the LDS accesses of one wavefront (its lanes exchange data through a
+// region no other wavefront touches): a compiler-level barrier plus a
+// wavefront-scope fence; no s_barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // index of the calling wavefront in its work-group, as a wave-uniform value
 // (lets the compiler keep row offsets in scalar registers)
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
@@ -231,7 +242,11 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
         if (lane == 0) rmax[wv] = amax;
     }
-    __syncthreads();
+    // each wavefront stages its own segment; only the R > 1 exponent needs the others
+    if constexpr (R > 1 && FX)
+        __syncthreads();
+    else
+        wave_lds_sync();
     // fixed-point exponent of this row: |out| <= max|x| * l1 < 2^(ilogb + 1)
     int ex = 0;
     if constexpr (FX) {
@@ -404,13 +419,13 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 #pragma unroll
         for (int j = 0; j < C; ++j) {
             if constexpr (FX) {
-                const double q = fmin(fmax(rint(ldexp(ys[j], ex)), -2147483648.0), 2147483647.0);
-                lds[lane * LP + j] = __int_as_float((int)q);
+                // |ys 2^ex| < 2^31 by the choice of ex (finite inputs)
+                lds[lane * LP + j] = __int_as_float((int)rint(ldexp((double)ys[j], ex)));
             } else {
                 lds[lane * LP + j] = ys[j];
             }
         }
-        __syncthreads();
+        wave_lds_sync();  // the segment in LDS belongs to this wavefront alone
         uint32_t *dst = static_cast<uint32_t *>(out_v) + (int64_t)s * plane_stride +
                         (int64_t)(row_ok ? row : 0) * out_pitch;
 #pragma unroll 4
@@ -419,7 +434,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
             const int col = seg0 + j;
             if (row_ok && col < W) dst[col] = __float_as_uint(lds[j + j / C]);
         }
-        __syncthreads();
+        wave_lds_sync();
     }
 }
 
@@ -467,11 +482,13 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m,
 // (b) carries: in place, every tile's forward zero state becomes the forward
 // state entering the tile from above, every backward zero state the backward
 // state entering it from below.
+constexpr int SCAN_T = 64;  // threads (columns) per scan work-group
+
 template <int K, bool FX>
-__global__ __launch_bounds__(256) void iir_col_scan_kernel(Mid<FX> m, int H, int W, int nty,
-                                                           double *__restrict__ st, Args a) {
-    constexpr int U = 4;  // tiles whose states are fetched together
-    const int col = blockIdx.x * 256 + threadIdx.x;
+__global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, int W, int nty,
+                                                              double *__restrict__ st, Args a) {
+    constexpr int U = 8;  // tiles whose states are fetched together
+    const int col = blockIdx.x * SCAN_T + threadIdx.x;
     const int s = blockIdx.y;
     const int dir = blockIdx.z;  // 0: forward from the top, 1: backward from the bottom
     if (col >= W) return;
@@ -520,25 +537,56 @@ __device__ __forceinline__ double lane_right_d(double v) {
                             __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
 }
 
+// Hardware work-group ids are dealt round-robin to the 8 XCDs (each with its
+// own L2).  Map them so that every XCD gets one contiguous run of logical
+// tiles: neighbouring column tiles (which share the cache lines at their
+// edges, both read and written) then meet in the same L2.
+__device__ __forceinline__ int xcd_logical_block(int hw, int n) {
+    constexpr int NX = 8;
+    const int xcd = hw % NX, slot = hw / NX;
+    const int q = n / NX, r = n % NX;
+    return xcd * q + min(xcd, r) + slot;
+}
+
+// copy one row of 64 lanes x 4 bytes from global memory straight into LDS
+// (no register round trip); the data is there after "s_waitcnt vmcnt(0)"
+__device__ __forceinline__ void row_to_lds(const void *g, uint32_t *l) {
+    __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void *)l, 4, 0, 0);
+}
+__device__ __forceinline__ void wait_lds_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 // (c) final pass of one 64-row tile per wavefront.  LAP = false: writes the
-// blur; in place is allowed (a tile reads and writes only its own rows).
-// LAP = true: writes sigma^2 (D20 + D02) of the blur; lanes cover columns
-// x0 - 1 .. x0 + 62 and lanes 1..62 write (in and out must not overlap).
-// The tile is finished in quarters of 16 rows so that only 16 float64 partial
-// outputs are live: one backward sweep over the lower three quarters records
-// the state entering each quarter from below; then every quarter, top first,
-// is swept backwards from its recorded state and finished by the forward
-// sweep, which runs through the whole tile.
+// blur; in place is allowed (a tile reads and writes only its own rows, and it
+// stages all of them before its first write).  LAP = true: writes
+// sigma^2 (D20 + D02) of the blur; lanes cover columns x0 - 1 .. x0 + 62 and
+// lanes 1..62 write (in and out must not overlap).
+// The tile (plus the rows just above and below it for LAP) is first copied
+// into LDS with direct global-to-LDS loads, so the whole tile is in flight at
+// once and no registers hold it.  It is then finished in quarters of 16 rows
+// so that only 16 float64 partial outputs are live: one backward sweep over the
+// lower three quarters records the state entering each quarter from below;
+// then every quarter, top first, is swept backwards from its recorded state
+// and finished by the forward sweep, which runs through the whole tile.
+constexpr int FIN_WPB = 4;  // wavefronts (tiles) per final-pass work-group
+
 template <int K, bool LAP, bool FX>
-__global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2, 8))) void iir_col_final_kernel(
-    Mid<FX> m, float *out, int64_t out_pitch, int64_t out_plane_stride, int H, int W, int nty,
+__global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
+    Mid<FX> m, float *out, int64_t out_pitch, int64_t out_plane_stride, int H, int W, int nty, int ntx,
     const double *__restrict__ st, Args a) {
     constexpr int QT = 16;
     constexpr int NQ = CT / QT;
+    constexpr int NR = LAP ? CT + 2 : CT;   // staged rows: (y0 - 1 if LAP) .. y0 + CT - 1 (.. y0 + CT if LAP)
+    constexpr int R0 = LAP ? 1 : 0;         // LDS row of tile row 0
+    __shared__ uint32_t tiles[FIN_WPB][NR * 64];
     const int lane = threadIdx.x & 63;
-    const int ty = blockIdx.y * COL_WPB + wave_id();
-    const int s = blockIdx.z;
-    const int col = LAP ? blockIdx.x * 62 - 1 + lane : blockIdx.x * 64 + lane;
+    const int wv = wave_id();
+    // logical block -> (column tile, group of FIN_WPB row tiles, scale), column tile fastest
+    const int ntyg = (nty + FIN_WPB - 1) / FIN_WPB;
+    const int lb = xcd_logical_block(blockIdx.x, ntx * ntyg * a.nscales);
+    const int tx = lb % ntx;
+    const int s = lb / (ntx * ntyg);
+    const int ty = ((lb / ntx) % ntyg) * FIN_WPB + wv;
+    const int col = LAP ? tx * 62 - 1 + lane : tx * 64 + lane;
     if (ty >= nty) return;
     const int ccol = min(max(col, 0), W - 1);
     const ScaleArgs &cf = a.s[s];
@@ -546,7 +594,13 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
     const int y0 = ty * CT;
     const int y1 = min(y0 + CT, H);
     const int len = y1 - y0;
-    auto xin = [&](int y) { return m.at(s, y, ccol); };
+    uint32_t *lt = tiles[wv];
+    // rows outside the image are clamped copies; they are never used as data
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+        const int y = min(max(y0 - R0 + r, 0), H - 1);
+        row_to_lds(m.ptr(s, y, ccol), lt + r * 64);
+    }
     const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
     double vf[K], ub[NQ][K];
     {
@@ -557,13 +611,21 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
             ub[NQ - 1][k] = o[(int64_t)(K + k) * W];
         }
     }
+    double sc_above = 1.0, sc_below = 1.0;
+    if constexpr (LAP && FX) {
+        sc_above = m.row_scale(max(y0 - 1, 0));
+        sc_below = m.row_scale(min(y1, H - 1));
+    }
+    wait_lds_dma();
+    // sample of tile row j (j = -1 and j = len only with LAP)
+    auto X = [&](int j) { return m.cvt(lt[(j + R0) * 64 + lane], read_lane_d(lsc, j)); };
     float *dst = out + (int64_t)s * out_plane_stride;
     const double sig2 = cf.sig2;
     const bool wr = LAP ? (lane >= 1 && lane <= 62 && col < W) : col < W;
     // y- of row y1 (below the tile) for the Laplacian's last row
     double t_bot = 0.0;
     if (LAP && y1 < H) {
-        const double xb = xin(y1);
+        const double xb = m.cvt(lt[(len + R0) * 64 + lane], sc_below);
         double u[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) u[k] = ub[NQ - 1][k];
@@ -579,8 +641,7 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
         double bm = 0.0, bc = 0.0;  // sliding B(n-1), B(n) for the Laplacian
         auto load_q = [&](int q) {
 #pragma unroll
-            for (int i = 0; i < QT; ++i)
-                xd[i] = m.cvt(m.raw(s, min(y0 + q * QT + i, H - 1), ccol), read_lane_d(lsc, q * QT + i));
+            for (int i = 0; i < QT; ++i) xd[i] = valid(q * QT + i) ? X(q * QT + i) : 0.0;
         };
         auto emit = [&](int y, double bmv, double bcv, double bnv) {
             const double bl = lane_left_d(bcv);
@@ -591,16 +652,13 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
         // states entering each quarter from below
 #pragma unroll
         for (int q = NQ - 1; q >= 1; --q) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) ub[q - 1][k] = ub[q][k];
             if (FULL || q * QT < len) {
                 load_q(q);
 #pragma unroll
-                for (int k = 0; k < K; ++k) ub[q - 1][k] = ub[q][k];
-#pragma unroll
                 for (int i = QT - 1; i >= 0; --i)
                     if (valid(q * QT + i)) cas_step(p, ub[q - 1], xd[i]);
-            } else {
-#pragma unroll
-                for (int k = 0; k < K; ++k) ub[q - 1][k] = ub[q][k];
             }
         }
 #pragma unroll
@@ -619,7 +677,7 @@ __global__ __launch_bounds__(COL_WPB * 64) __attribute__((amdgpu_waves_per_eu(2,
             }
             if constexpr (LAP) {
                 if (q == 0 && y0 > 0) {  // B of the row above the tile; u is u(y0)
-                    const double xa = xin(y0 - 1);
+                    const double xa = m.cvt(lt[lane], sc_above);
                     const double ta = fma(cf.b0, xa, cas_out(cf, u));
                     double v[K];
 #pragma unroll
@@ -744,18 +802,21 @@ hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t p
                        st, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    dim3 g2((unsigned)((W + 255) / 256), S, 2);
-    hipLaunchKernelGGL((iir_col_scan_kernel<K, FX>), g2, dim3(256), 0, stream, m, (int)H, (int)W, nty, st, a);
+    dim3 g2((unsigned)((W + SCAN_T - 1) / SCAN_T), S, 2);
+    hipLaunchKernelGGL((iir_col_scan_kernel<K, FX>), g2, dim3(SCAN_T), 0, stream, m, (int)H, (int)W, nty, st, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
+    const int ntyg = (nty + FIN_WPB - 1) / FIN_WPB;
     if (lap) {
-        dim3 g3((unsigned)((W + 61) / 62), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
-        hipLaunchKernelGGL((iir_col_final_kernel<K, true, FX>), g3, dim3(COL_WPB * 64), 0, stream, m, out, pitch,
-                           plane_stride, (int)H, (int)W, nty, st, a);
+        const int ntx = (int)((W + 61) / 62);
+        const unsigned nb = (unsigned)ntx * (unsigned)ntyg * S;
+        hipLaunchKernelGGL((iir_col_final_kernel<K, true, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream, m, out,
+                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a);
     } else {
-        dim3 g3((unsigned)((W + 63) / 64), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
-        hipLaunchKernelGGL((iir_col_final_kernel<K, false, FX>), g3, dim3(COL_WPB * 64), 0, stream, m, out, pitch,
-                           plane_stride, (int)H, (int)W, nty, st, a);
+        const int ntx = (int)((W + 63) / 64);
+        const unsigned nb = (unsigned)ntx * (unsigned)ntyg * S;
+        hipLaunchKernelGGL((iir_col_final_kernel<K, false, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream, m, out,
+                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a);
     }
     return hipGetLastError();
 }
