@@ -186,24 +186,31 @@ def main() -> int:
                              device=dev)
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
 
-        def fir_step(ev):
-            ev[0].record(stream)
-            check(L.fdvm_blur_fir(x.data_ptr(), P.U16, H, W, W, B.data_ptr(), W, H * W, taps.ctypes.data_as(dp),
-                                  half.ctypes.data_as(ip), off.ctypes.data_as(ip), S, P.BC_REPLICATE,
-                                  P.FIR_DIRECT, ws_fir.data_ptr(), ws_fir.numel(), sp), "fir")
-            ev[1].record(stream)
-            check(L.fdvm_highpass(B.data_ptr(), H, W, W, H * W, S, sigmas_c, P.HP_LAPLACIAN, 1, V.data_ptr(),
-                                  H * W, sp), "highpass")
-            ev[2].record(stream)
-            detect_into(ev[3])
+        def fir_step_for(algo):
+            def fir_step(ev):
+                ev[0].record(stream)
+                check(L.fdvm_blur_fir(x.data_ptr(), P.U16, H, W, W, B.data_ptr(), W, H * W,
+                                      taps.ctypes.data_as(dp), half.ctypes.data_as(ip), off.ctypes.data_as(ip), S,
+                                      P.BC_REPLICATE, algo, ws_fir.data_ptr(), ws_fir.numel(), sp), "fir")
+                ev[1].record(stream)
+                check(L.fdvm_highpass(B.data_ptr(), H, W, W, H * W, S, sigmas_c, P.HP_LAPLACIAN, 1, V.data_ptr(),
+                                      H * W, sp), "highpass")
+                ev[2].record(stream)
+                detect_into(ev[3])
+            return fir_step
 
         fsteps = max(5, args.steps // 10)
-        ftot, _, fper = timed(fir_step, 4, fsteps, max(1, args.warmup // 5))
-        fms = ftot / fsteps
-        fir = {"value": round(mpx / (fms / 1e3), 1), "ms_per_step": round(fms, 4), "blur_ms": round(fper[0], 4),
-               "algo": "direct", "kind": "colored_sg", "taps": [int(2 * k + 1) for k in half],
-               "steps": fsteps}
-        log(f"FIR: {fms:.4f} ms/step, {fir['value']:.0f} Mpx*scales/s (blur {fper[0]:.3f} ms)")
+        fir = {"kind": "colored_sg", "taps": [int(2 * k + 1) for k in half], "steps": fsteps}
+        # useful flops of the blur: 2 (2K + 1) per pixel per 1-D pass, two passes
+        useful = sum(4.0 * (2 * int(k) + 1) for k in half) * H * W
+        for name, algo in (("direct", P.FIR_DIRECT), ("mfma", P.FIR_TOEPLITZ_MFMA)):
+            ftot, _, fper = timed(fir_step_for(algo), 4, fsteps, max(1, args.warmup // 5))
+            fms = ftot / fsteps
+            fir[name] = {"value": round(mpx / (fms / 1e3), 1), "ms_per_step": round(fms, 4),
+                         "blur_ms": round(fper[0], 4),
+                         "blur_useful_TFLOPs": round(useful / (fper[0] / 1e3) / 1e12, 2)}
+            log(f"FIR {name}: {fms:.4f} ms/step, {fir[name]['value']:.0f} Mpx*scales/s (blur {fper[0]:.3f} ms, "
+                f"{fir[name]['blur_useful_TFLOPs']} useful TFLOP/s)")
 
     # ---------------- CPU baseline: the FP64 oracle on the same frame
     cpu = None

@@ -211,12 +211,15 @@ fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
  *             written by fdvm_filter_design).  Taps must be symmetric.
  *   half_len  host int32[nscales], each in [1, FDVM_MAX_FIR_HALF].
  *   tap_offset host int32[nscales].
- *   algo      FDVM_FIR_DIRECT (LDS-staged direct convolution, float32) or
- *             FDVM_FIR_TOEPLITZ_MFMA (Toeplitz-block products on the matrix
- *             cores, float32 accumulation).
+ *   algo      FDVM_FIR_DIRECT (LDS-staged direct convolution, float32, x then
+ *             y) or FDVM_FIR_TOEPLITZ_MFMA (Toeplitz-block products on the
+ *             matrix cores, float32 operands and accumulation, y then x: the
+ *             two orders agree up to rounding for a separable filter with a
+ *             separable extension, Section 2).
  *   ws, ws_bytes device workspace of at least
  *             fdvm_workspace_bytes(FDVM_OP_BLUR_FIR, H, W, nscales, maxK) bytes
- *             (holds tap tables and the row-pass intermediate).
+ *             (the first-pass planes: one for FDVM_FIR_DIRECT, nscales
+ *             transposed ones for FDVM_FIR_TOEPLITZ_MFMA).
  * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM (workspace too small) /
  * FDVM_EDEVICE.
  */

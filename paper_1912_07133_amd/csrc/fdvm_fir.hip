@@ -19,10 +19,6 @@
 
 namespace fdvm {
 
-hipError_t launch_fir_mfma(const float *src, int64_t H, int64_t W, int64_t pitch, float *dst,
-                           int64_t out_pitch, const float *taps_half, int K, int boundary,
-                           bool transpose_in, hipStream_t st);
-
 namespace {
 
 constexpr int FIR_R = 8;          // outputs per thread
@@ -191,9 +187,11 @@ hipError_t rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, float 
 }  // namespace
 
 size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half) {
-    (void)nscales;
     (void)max_half;
-    return ((size_t)H * (size_t)W * sizeof(float) + 255) & ~(size_t)255;
+    // direct: one row-pass plane; Toeplitz/MFMA: one transposed plane per scale
+    const size_t direct = ((size_t)H * (size_t)W * sizeof(float) + 255) & ~(size_t)255;
+    const size_t mfma = fir_mfma_workspace_bytes(H, W, nscales);
+    return direct > mfma ? direct : mfma;
 }
 
 hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, float *out,
@@ -203,34 +201,28 @@ hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t i
     (void)ws_bytes;
     float *tmp = static_cast<float *>(ws);
     const int64_t tmp_pitch = W;
+    if (algo == FDVM_FIR_TOEPLITZ_MFMA)
+        return launch_fir_mfma(in, dtype, H, W, in_pitch, tmp, out, out_pitch, plane_stride, taps, half_len,
+                               tap_offset, nscales, boundary, st);
     for (int s = 0; s < nscales; ++s) {
+        float *dst = out + (int64_t)s * plane_stride;
         Half hh;
         hh.K = half_len[s];
         for (int m = 0; m <= hh.K; ++m) hh.h[m] = (float)taps[tap_offset[s] + hh.K + m];
-        float *dst = out + (int64_t)s * plane_stride;
         hipError_t e = hipSuccess;
-        if (algo == FDVM_FIR_TOEPLITZ_MFMA && dtype == FDVM_F32) {
-            e = launch_fir_mfma(static_cast<const float *>(in), H, W, in_pitch, tmp, tmp_pitch, hh.h, hh.K,
-                                boundary, false, st);
-        } else {
-            switch (dtype) {
-                case FDVM_U16: e = rows_t<uint16_t>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
-                case FDVM_F32: e = rows_t<float>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
-                case FDVM_F16: e = rows_t<_Float16>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
-                case FDVM_BF16: e = rows_t<bf16_t>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
-                default: return hipErrorInvalidValue;
-            }
+        switch (dtype) {
+            case FDVM_U16: e = rows_t<uint16_t>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
+            case FDVM_F32: e = rows_t<float>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
+            case FDVM_F16: e = rows_t<_Float16>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
+            case FDVM_BF16: e = rows_t<bf16_t>(in, H, W, in_pitch, tmp, tmp_pitch, boundary, hh, st); break;
+            default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;
-        if (algo == FDVM_FIR_TOEPLITZ_MFMA) {
-            e = launch_fir_mfma(tmp, H, W, tmp_pitch, dst, out_pitch, hh.h, hh.K, boundary, true, st);
-        } else {
-            const size_t lds = sizeof(float) * (2 * hh.K + 4 * COL_R + 1);
-            dim3 grid((unsigned)((W + 63) / 64), (unsigned)((H + 4 * COL_R - 1) / (4 * COL_R)));
-            hipLaunchKernelGGL(fir_cols_kernel, grid, dim3(256), lds, st, tmp, tmp_pitch, dst, out_pitch,
-                               (int)H, (int)W, boundary, hh);
-            e = hipGetLastError();
-        }
+        const size_t lds = sizeof(float) * (2 * hh.K + 4 * COL_R + 1);
+        dim3 grid((unsigned)((W + 63) / 64), (unsigned)((H + 4 * COL_R - 1) / (4 * COL_R)));
+        hipLaunchKernelGGL(fir_cols_kernel, grid, dim3(256), lds, st, tmp, tmp_pitch, dst, out_pitch, (int)H,
+                           (int)W, boundary, hh);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

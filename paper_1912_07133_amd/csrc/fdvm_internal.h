@@ -74,6 +74,13 @@ hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch,
                          int32_t *count, void *ws, hipStream_t stream);
 
 bool fir_mfma_available();
+// Toeplitz-block FIR on the matrix cores: y pass of `in` into tmp (nscales
+// transposed W x H planes), x pass of tmp transposed back into `out`.
+size_t fir_mfma_workspace_bytes(int64_t H, int64_t W, int nscales);
+hipError_t launch_fir_mfma(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, float *tmp,
+                           float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                           const int32_t *half_len, const int32_t *tap_offset, int nscales, int boundary,
+                           hipStream_t stream);
 size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half);
 hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
                       float *out, int64_t out_pitch, int64_t plane_stride,

@@ -1,4 +1,6 @@
-"""GPU parity of fdvm_blur_fir (Eq A5, x then y) against the oracle.
+"""GPU parity of fdvm_blur_fir (Eq A5, separable) against the oracle, for both
+algorithms: direct LDS-staged convolution and the Toeplitz-block products on
+the matrix cores (float32 operands and accumulation).
 
 Small frames are compared everywhere; the 2048x2048 x 8-scale frame (the
 benchmark's FIR configuration, coloured SG of length 6 sigma + 1) is compared
@@ -23,28 +25,35 @@ def oracle_taps(kind, sigma, K=None):
     return design.gaussian_taps(sigma, K if K else design.fir_half_length(sigma))
 
 
-@pytest.mark.parametrize("shape", [(1, 1), (5, 300), (300, 5), (77, 131), (256, 2500)])
+ALGOS = {"direct": P.FIR_DIRECT, "mfma": P.FIR_TOEPLITZ_MFMA}
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (5, 300), (300, 5), (77, 131), (256, 2500), (129, 65)])
 @pytest.mark.parametrize("kind", ["sg", "gaussian"])
-def test_fir_direct_ragged(shape, kind):
+@pytest.mark.parametrize("algo", list(ALGOS))
+def test_fir_ragged(shape, kind, algo):
     H, W = shape
-    say(f"case: fir {kind} {H}x{W}")
+    say(f"case: fir {algo} {kind} {H}x{W}")
     rng = np.random.default_rng(H + 3 * W)
     img = (rng.random((H, W)) * 10).astype(np.float32)
     # the coloured SG needs omega_c = 3/sigma < pi (a non-empty stopband)
     sigmas = [1.2, 2.5, 11.0] if kind == "sg" else [0.7, 2.5, 11.0]
     for bc in ("replicate", "zero"):
-        got = P.blur_fir(torch.from_numpy(img).cuda(), sigmas, kind=kind, boundary=bc).cpu().numpy()
+        got = P.blur_fir(torch.from_numpy(img).cuda(), sigmas, kind=kind, boundary=bc,
+                         algo=ALGOS[algo]).cpu().numpy()
         ref = np.stack([filtering.blur_2d(img.astype(np.float64), oracle_taps(kind, s), bc) for s in sigmas])
         assert_planes_close(got, ref, what=f"{bc} scale")
 
 
-def test_fir_explicit_lengths_precision_config():
+@pytest.mark.parametrize("algo", list(ALGOS))
+def test_fir_explicit_lengths_precision_config(algo):
     """FIR lengths 33, 65, 129, 257 (sigma = K/3) on a normalised frame."""
-    say("case: fir lengths 33..257")
+    say(f"case: fir {algo} lengths 33..257")
     frame = syn.normalised_frame(700, 900, 3, nblobs=30).astype(np.float32)
     Ks = [16, 32, 64, 128]
     sig = [K / 3 for K in Ks]
-    got = P.blur_fir(torch.from_numpy(frame).cuda(), sig, kind="sg", half_lens=Ks).cpu().numpy()
+    got = P.blur_fir(torch.from_numpy(frame).cuda(), sig, kind="sg", half_lens=Ks,
+                     algo=ALGOS[algo]).cpu().numpy()
     ref = np.stack([filtering.blur_2d(frame.astype(np.float64), design.colored_sg_taps(s, K=K))
                     for s, K in zip(sig, Ks)])
     assert_planes_close(got, ref)
@@ -63,12 +72,13 @@ def sampled_2d(img64, h, points):
     return np.array(out)
 
 
-def test_full_frame_fir_sampled():
+@pytest.mark.parametrize("algo", list(ALGOS))
+def test_full_frame_fir_sampled(algo):
     cfg = syn.FULL_FRAME
-    say("case: fir full frame 2048x2048 u16 8 scales (sampled)")
+    say(f"case: fir {algo} full frame 2048x2048 u16 8 scales (sampled)")
     frame = syn.aerial_frame(cfg["H"], cfg["W"], cfg["seed"])
     x = torch.from_numpy(frame.view(np.int16)).cuda()
-    got = P.blur_fir(x, cfg["sigmas"], kind="sg").cpu().numpy()
+    got = P.blur_fir(x, cfg["sigmas"], kind="sg", algo=ALGOS[algo]).cpu().numpy()
     rng = np.random.default_rng(0)
     pts = [(0, 0), (2047, 2047), (0, 2047), (5, 1000), (1024, 3)] + \
           [tuple(p) for p in rng.integers(0, 2048, (60, 2))]
@@ -77,3 +87,22 @@ def test_full_frame_fir_sampled():
         ref = sampled_2d(f64, design.colored_sg_taps(sigma), pts)
         g = np.array([got[s, i, j] for i, j in pts])
         assert np.max(np.abs(g - ref)) <= 1e-5 * np.max(np.abs(f64)), s
+
+
+@pytest.mark.parametrize("dtype", ["f16", "bf16", "u16"])
+def test_fir_mfma_input_dtypes(dtype):
+    say(f"case: fir mfma dtype {dtype} 150x333")
+    rng = np.random.default_rng(11)
+    if dtype == "u16":
+        a = rng.integers(0, 4096, (150, 333)).astype(np.uint16)
+        x = torch.from_numpy(a.view(np.int16)).cuda()
+        x64 = a.astype(np.float64)
+    else:
+        t = torch.from_numpy(rng.random((150, 333)).astype(np.float32))
+        t = t.to(torch.float16 if dtype == "f16" else torch.bfloat16)
+        x = t.cuda()
+        x64 = t.float().numpy().astype(np.float64)
+    sig = [1.5, 6.0, 30.0]
+    got = P.blur_fir(x, sig, kind="sg", algo=P.FIR_TOEPLITZ_MFMA).cpu().numpy()
+    ref = np.stack([filtering.blur_2d(x64, design.colored_sg_taps(s)) for s in sig])
+    assert_planes_close(got, ref)
