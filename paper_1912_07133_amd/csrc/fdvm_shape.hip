@@ -16,6 +16,7 @@
 //   emit  -- every block rescans its words and writes the records.
 // The list therefore comes out ordered by (scale, y, x).
 #include <cmath>
+#include <type_traits>
 
 #include "fdvm_internal.h"
 
@@ -82,13 +83,64 @@ __device__ __forceinline__ float lane_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-// NaN marks a missing neighbour (outside the stack); fminf/fmaxf skip it.
+constexpr int DT_NPL = 4;  // planes in each wavefront's LDS ring (the one in use + 3 in flight)
+
+// copy 64 lanes x 4 bytes from global memory straight into LDS (lane n to
+// l[n]); complete once vmcnt has dropped past it
+__device__ __forceinline__ void row_to_lds(const float *g, uint32_t *l) {
+    __builtin_amdgcn_global_load_lds((const void *)g, (__attribute__((address_space(3))) void *)l, 4, 0, 0);
+}
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+// the calling lane's word of the DT_ROWS + 2 staged rows of one plane, read
+// and waited for in one block: a plain LDS load would make the compiler wait
+// for every copy still in flight (it cannot tell which LDS words they write)
+static_assert(DT_ROWS + 2 == 10, "read10 reads ten rows");
+__device__ __forceinline__ void read10(const uint32_t *p, uint32_t (&r)[10]) {
+    const uint32_t a = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) uint32_t *)p;
+    asm volatile(
+        "ds_read_b32 %0, %10\n ds_read_b32 %1, %10 offset:256\n ds_read_b32 %2, %10 offset:512\n"
+        " ds_read_b32 %3, %10 offset:768\n ds_read_b32 %4, %10 offset:1024\n ds_read_b32 %5, %10 offset:1280\n"
+        " ds_read_b32 %6, %10 offset:1536\n ds_read_b32 %7, %10 offset:1792\n ds_read_b32 %8, %10 offset:2048\n"
+        " ds_read_b32 %9, %10 offset:2304\n s_waitcnt lgkmcnt(0)"
+        : "=&v"(r[0]), "=&v"(r[1]), "=&v"(r[2]), "=&v"(r[3]), "=&v"(r[4]), "=&v"(r[5]), "=&v"(r[6]), "=&v"(r[7]),
+          "=&v"(r[8]), "=&v"(r[9])
+        : "v"(a)
+        : "memory");
+}
+
+// Order-preserving integer key of a float32 (finite or infinite): k(a) < k(b)
+// exactly when a < b, and k(+0) = k(-0) = 0.  Integer minima and maxima then
+// need no NaN handling, and a missing neighbour is a sentinel key that can
+// never win: INT32_MAX for minima, INT32_MIN for maxima.
+__device__ __forceinline__ int fkey(float v) {
+    const int b = __float_as_int(v);
+    const int sgn = b >> 31;
+    return ((b & 0x7fffffff) ^ sgn) - sgn;
+}
+// key of lane (l - 1) / (l + 1) (gfx9 DPP wave_shr:1 / wave_shl:1); the end
+// lanes read 0, which only ever feeds their own (unused) results
+__device__ __forceinline__ int key_left(int k) { return __builtin_amdgcn_mov_dpp(k, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int key_right(int k) { return __builtin_amdgcn_mov_dpp(k, 0x130, 0xf, 0xf, true); }
+
+// The planes reach LDS by direct global-to-LDS copies issued DT_NPL - 1
+// planes ahead of use; the mask words of the wavefront collect in LDS and are
+// written once at the end (no stores interleave with the counted copies).
+// Per plane and output row the kernel keeps the 3 x 3 minimum / maximum key
+// (centre included) and the 8-neighbour ones (centre excluded); the planes
+// rotate through three register roles (previous, current, next), so the
+// scale loop is unrolled by three.
 __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float *__restrict__ V, int64_t pitch,
                                                                      int64_t plane_stride, int S, int H, int W,
                                                                      float tau, int border,
                                                                      unsigned long long *__restrict__ mask,
                                                                      int ntx) {
     constexpr int RB = DT_ROWS;
+    constexpr int KMAX = 0x7fffffff, KMIN = (int)0x80000000;
+    __shared__ uint32_t ring[DT_WAVES][DT_NPL][(RB + 2) * 64];
+    __shared__ unsigned long long words[DT_WAVES][FDVM_MAX_SCALES * RB];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int tx = blockIdx.x;
@@ -97,96 +149,116 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     if (y0 >= H) return;
     const bool xin = x >= 0 && x < W;
     const int cx = min(max(x, 0), W - 1);
-    const float qnan = __int_as_float(0x7fc00000);
-    // rows y0-1 .. y0+RB of the plane, NaN outside the image
-    auto load_plane = [&](int s, float (&v)[RB + 2]) {
-        const float *P = V + (int64_t)s * plane_stride;   // wave-uniform
+    uint32_t *rg = &ring[wv][0][0];
+    // rows y0-1 .. y0+RB of plane min(s, S - 1) into ring slot s % DT_NPL
+    auto request = [&](int s) {
+        const float *P = V + (int64_t)min(s, S - 1) * plane_stride + cx;   // wave-uniform plane
+        uint32_t *slot = rg + (s % DT_NPL) * (RB + 2) * 64;
 #pragma unroll
         for (int r = 0; r < RB + 2; ++r) {
-            const int y = y0 - 1 + r;
-            const float t = P[(int64_t)min(max(y, 0), H - 1) * pitch + cx];
-            v[r] = (xin && y >= 0 && y < H) ? t : qnan;
+            const int y = min(max(y0 - 1 + r, 0), H - 1);
+            row_to_lds(P + (int64_t)y * pitch, slot + r * 64);
         }
     };
-    // separable 3x3 min / max (centre included) for rows y0 .. y0+RB-1, and
-    // the 8-neighbour min / max (centre excluded)
-    float cur[RB + 2], nxt[RB + 2], pre[RB + 2];
-    float m9p[RB], M9p[RB];             // previous plane's 3x3 min / max
-    float m9c[RB], M9c[RB], m8c[RB], M8c[RB];
-    bool have_prev = false;
-    load_plane(0, cur);
-    if (S > 1) load_plane(1, pre);      // raw samples one plane ahead
-    auto planes_stats = [&](const float (&v)[RB + 2], float (&m9)[RB], float (&M9)[RB], float (&m8)[RB],
-                            float (&M8)[RB]) {
-        float rmin[RB + 2], rmax[RB + 2];
+    constexpr int AHEAD = (DT_NPL - 1) * (RB + 2);  // copies issued after the plane awaited
+    struct Plane {
+        int c[RB];               // centre keys of the output rows
+        int m9[RB], M9[RB];      // 3 x 3 minimum / maximum
+        int m8[RB], M8[RB];      // the same without the centre
+    };
+    // statistics of plane s (its copies must have landed).  EDGE: the band
+    // touches the image border (some rows or lanes outside get sentinels);
+    // otherwise every staged sample is inside and no test is needed.
+    auto stats = [&](int s, Plane &pl, auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        uint32_t raw[RB + 2];
+        read10(rg + (s % DT_NPL) * (RB + 2) * 64 + lane, raw);
+        int rmin[RB + 2], rmax[RB + 2], lrmin[RB + 2], lrmax[RB + 2];
 #pragma unroll
         for (int r = 0; r < RB + 2; ++r) {
-            const float l = lane_left(v[r]);
-            const float rr = lane_right(v[r]);
-            const float lr_min = fminf(l, rr), lr_max = fmaxf(l, rr);
-            rmin[r] = fminf(lr_min, v[r]);
-            rmax[r] = fmaxf(lr_max, v[r]);
-            if (r >= 1 && r <= RB) {
-                m8[r - 1] = lr_min;   // completed below with the rows above / below
-                M8[r - 1] = lr_max;
+            const int k = fkey(__uint_as_float(raw[r]));
+            if constexpr (EDGE) {
+                const int y = y0 - 1 + r;
+                const bool yin = y >= 0 && y < H;   // wave-uniform
+                const int kmin = xin ? k : KMAX, kmax = xin ? k : KMIN;
+                const int lmin = min(key_left(kmin), key_right(kmin));
+                const int lmax = max(key_left(kmax), key_right(kmax));
+                lrmin[r] = yin ? lmin : KMAX;
+                lrmax[r] = yin ? lmax : KMIN;
+                rmin[r] = yin ? min(lmin, kmin) : KMAX;
+                rmax[r] = yin ? max(lmax, kmax) : KMIN;
+            } else {
+                const int kl = key_left(k), kr = key_right(k);
+                lrmin[r] = min(kl, kr);
+                lrmax[r] = max(kl, kr);
+                rmin[r] = min(min(kl, kr), k);
+                rmax[r] = max(max(kl, kr), k);
             }
+            if (r >= 1 && r <= RB) pl.c[r - 1] = k;
         }
+        // three-operand minima / maxima with single-use inner terms (v_min3 / v_max3)
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            const float a = fminf(rmin[r], rmin[r + 2]);
-            const float b = fmaxf(rmax[r], rmax[r + 2]);
-            m8[r] = fminf(m8[r], a);
-            M8[r] = fmaxf(M8[r], b);
-            m9[r] = fminf(a, rmin[r + 1]);
-            M9[r] = fmaxf(b, rmax[r + 1]);
+            pl.m8[r] = min(min(rmin[r], lrmin[r + 1]), rmin[r + 2]);
+            pl.M8[r] = max(max(rmax[r], lrmax[r + 1]), rmax[r + 2]);
+            pl.m9[r] = min(min(rmin[r], rmin[r + 1]), rmin[r + 2]);
+            pl.M9[r] = max(max(rmax[r], rmax[r + 1]), rmax[r + 2]);
         }
     };
-    planes_stats(cur, m9c, M9c, m8c, M8c);
+    const int kneg = fkey(-tau), kpos = fkey(tau);
     const bool xout = lane >= 1 && lane <= 62 && x < W && x >= border && x < W - border;
-    for (int s = 0; s < S; ++s) {
-        float m9n[RB], M9n[RB], m8n[RB], M8n[RB];
-        const bool have_next = s + 1 < S;
-        if (have_next) {
-#pragma unroll
-            for (int r = 0; r < RB + 2; ++r) nxt[r] = pre[r];
-            if (s + 2 < S) load_plane(s + 2, pre);   // in flight while s + 1 is used
-            planes_stats(nxt, m9n, M9n, m8n, M8n);
-        }
-        unsigned long long *mrow = mask + ((int64_t)s * H + y0) * ntx + tx;
+    unsigned long long *wd = words[wv];
+    // decisions at plane s from its neighbours in scale (absent ones skipped)
+    auto decide = [&](int s, const Plane &pv, const Plane &pc, const Plane &pn, bool hp, bool hn) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int y = y0 + r;
-            const float v = cur[r + 1];
-            float lo = m8c[r], hi = M8c[r];
-            if (have_prev) {
-                lo = fminf(lo, m9p[r]);
-                hi = fmaxf(hi, M9p[r]);
-            }
-            if (have_next) {
-                lo = fminf(lo, m9n[r]);
-                hi = fmaxf(hi, M9n[r]);
-            }
+            const int lo = min(min(pc.m8[r], hp ? pv.m9[r] : KMAX), hn ? pn.m9[r] : KMAX);
+            const int hi = max(max(pc.M8[r], hp ? pv.M9[r] : KMIN), hn ? pn.M9[r] : KMIN);
+            const int k = pc.c[r];
             const bool inside = xout && y < H && y >= border && y < H - border;
             // no neighbour at all (1 x 1 x 1 stack) compares as "strict" too
-            const bool bright = inside && v <= -tau && !(v >= lo);
-            const bool dark = inside && v >= tau && !(v <= hi);
+            const bool bright = inside && k <= kneg && k < lo;
+            const bool dark = inside && k >= kpos && k > hi;
             const unsigned long long bits = __ballot(bright || dark) >> 1;  // lanes 1..62 -> bits 0..61
-            if (lane == 0 && y < H) mrow[(int64_t)r * ntx] = bits;
+            if (lane == 0) wd[s * RB + r] = bits;
         }
-        if (have_next) {
+    };
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                m9p[r] = m9c[r];
-                M9p[r] = M9c[r];
-                m9c[r] = m9n[r];
-                M9c[r] = M9n[r];
-                m8c[r] = m8n[r];
-                M8c[r] = M8n[r];
-            }
-#pragma unroll
-            for (int r = 0; r < RB + 2; ++r) cur[r] = nxt[r];
-            have_prev = true;
+    for (int q = 0; q < DT_NPL; ++q) request(q);
+    auto run = [&](auto edge_tag) {
+        Plane P0, P1, P2;
+        wait_vm<AHEAD>();   // plane 0
+        stats(0, P0, edge_tag);
+        // step at plane s: plane s + 1 is needed now; plane s's slot is free
+        // (its statistics are in registers)
+        auto step = [&](int s, Plane &pv, Plane &pc, Plane &pn) {
+            request(s + DT_NPL);
+            wait_vm<AHEAD>();
+            const bool hn = s + 1 < S;
+            if (hn) stats(s + 1, pn, edge_tag);
+            decide(s, pv, pc, pn, s > 0, hn);
+        };
+        for (int s = 0; s < S; s += 3) {
+            step(s, P2, P0, P1);
+            if (s + 1 >= S) break;
+            step(s + 1, P0, P1, P2);
+            if (s + 2 >= S) break;
+            step(s + 2, P1, P2, P0);
         }
+    };
+    // a band is interior when its 64 lanes and RB + 2 rows all lie in the image
+    const bool interior = x - lane >= 0 && x - lane + 63 < W && y0 >= 1 && y0 + RB < H;  // wave-uniform
+    if (interior)
+        run(std::false_type{});
+    else
+        run(std::true_type{});
+    wait_vm<0>();  // no copy may land in LDS after this wavefront is gone
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    for (int k = lane; k < S * RB; k += 64) {
+        const int s = k / RB, r = k % RB;
+        if (y0 + r < H) mask[((int64_t)s * H + y0 + r) * ntx + tx] = wd[k];
     }
 }
 
