@@ -525,16 +525,17 @@ __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, 
 
 // value of lane l-1 (left) / l+1 (right) of a double across the whole
 // wavefront (gfx9 DPP wave_shr:1 / wave_shl:1 on both halves); the end lanes
-// get their own value back
+// read 0, which only reaches their own results (lanes 0 and 63 of a
+// Laplacian tile are overlap columns that are never written)
 __device__ __forceinline__ double lane_left_d(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xf, 0xf, false),
-                            __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xf, 0xf, false));
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x138, 0xf, 0xf, true),
+                            __builtin_amdgcn_mov_dpp(lo, 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ double lane_right_d(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
-    return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xf, 0xf, false),
-                            __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xf, 0xf, false));
+    return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, 0x130, 0xf, 0xf, true),
+                            __builtin_amdgcn_mov_dpp(lo, 0x130, 0xf, 0xf, true));
 }
 
 // Hardware work-group ids are dealt round-robin to the 8 XCDs (each with its
