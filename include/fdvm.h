@@ -266,11 +266,54 @@ fdvm_status fdvm_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch
  *             exceed cap; only the first cap are written)
  *   ws        device workspace >= fdvm_workspace_bytes(FDVM_OP_DETECT, ...)
  * The call is asynchronous; the caller reads *count_dev after synchronising
- * and treats count > cap as overflow.  tau >= 0, border >= 0.
+ * and treats count > cap as overflow.  tau >= 0, border >= 0.  The planes
+ * must hold no NaN (the comparisons run on order-preserving integer keys).
  */
 fdvm_status fdvm_detect_blobs(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                               int nscales, float tau, int border, fdvm_blob *out_dev, int32_t cap,
                               int32_t *count_dev, void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------ batch
+ * One call over many frames of uneven size (Section 2's filter bank per frame,
+ * the same scales for all): for every frame, the fused repeated-pole blur and
+ * normalised Laplacian (as fdvm_iir_laplacian) and the multi-scale extrema
+ * (as fdvm_detect_blobs).  The frames are spread over up to nlanes internal
+ * streams that fork from and join back into `stream` through events, so the
+ * whole batch can be captured into one HIP graph by capturing `stream`.
+ */
+typedef struct {
+    const void *data;     /* device, H x W elements of type dtype, row pitch `pitch` */
+    int32_t dtype;        /* fdvm_dtype */
+    int32_t H, W;         /* 1 <= H <= 65535, 1 <= W <= 16384 */
+    int32_t row_chunk;    /* row-pass samples per lane: 0 = chosen from W, else 8, 16 or 32 */
+    int64_t pitch;        /* elements, >= W */
+    fdvm_blob *out;       /* device, capacity cap, filled in (scale, y, x) order */
+    int32_t *count;       /* device int32[1]: true number of detections of this frame */
+    int32_t cap;
+    int32_t reserved;
+} fdvm_frame;
+
+#define FDVM_MAX_LANES 16
+
+/* Workspace for fdvm_batch_detect: per lane, the largest frame's x-pass
+ * planes, column states, row exponents, V planes and detection words. */
+size_t fdvm_batch_workspace_bytes(const fdvm_frame *frames, int nframes, int nscales, int nlanes);
+
+/*
+ * fdvm_batch_detect -- frames[i] (host array of nframes descriptors) with the
+ *   nscales IIR designs `filters`, boundary bc, threshold tau, border margin.
+ *   nlanes in [1, FDVM_MAX_LANES] concurrent lanes (frame i runs on lane
+ *   i % nlanes).  ws: device, >= fdvm_batch_workspace_bytes(...).  Frame
+ *   outputs as fdvm_detect_blobs (count may exceed cap).
+ *   The internal streams and events are created once per device and reused;
+ *   calls that overlap on one device must not share them (serialise them).
+ * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM / FDVM_EUNSUPPORTED /
+ * FDVM_EDEVICE as the single-frame calls; nothing is enqueued on a
+ * validation error.
+ */
+fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_filter *filters, int nscales,
+                              fdvm_boundary bc, float tau, int border, int nlanes, void *ws, size_t ws_bytes,
+                              void *stream);
 
 #ifdef __cplusplus
 }

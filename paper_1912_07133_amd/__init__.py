@@ -56,7 +56,18 @@ class Blob(ctypes.Structure):
                 ("polarity", ctypes.c_int32), ("value", ctypes.c_float)]
 
 
+class Frame(ctypes.Structure):
+    """fdvm_frame: one frame of a batch (device pointers)."""
+    _fields_ = [("data", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("row_chunk", ctypes.c_int32), ("pitch", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("count", ctypes.c_void_p), ("cap", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 BLOB_BYTES = ctypes.sizeof(Blob)
+MAX_LANES = 16
+BLOB_DTYPE = np.dtype([("y", np.int32), ("x", np.int32), ("scale", np.int32), ("polarity", np.int32),
+                       ("value", np.float32)])
 _lib = None
 
 
@@ -100,6 +111,12 @@ def lib() -> ctypes.CDLL:
         L.fdvm_detect_blobs.restype = ctypes.c_int
         L.fdvm_detect_blobs.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_float,
                                         ctypes.c_int, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.fdvm_batch_workspace_bytes.restype = ctypes.c_size_t
+        L.fdvm_batch_workspace_bytes.argtypes = [ctypes.POINTER(Frame), ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.fdvm_batch_detect.restype = ctypes.c_int
+        L.fdvm_batch_detect.argtypes = [ctypes.POINTER(Frame), ctypes.c_int, ctypes.POINTER(Filter), ctypes.c_int,
+                                        ctypes.c_int, ctypes.c_float, ctypes.c_int, ctypes.c_int, vp,
+                                        ctypes.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -360,11 +377,108 @@ def detect(frame, sigmas: Sequence[float], tau: float, kind: str = "iir", order:
     return detect_blobs(V, tau, border, cap), V
 
 
+# ------------------------------------------------------------------ batch
+class Batch:
+    """Many frames of uneven size through fdvm_batch_detect: per frame the
+    fused IIR blur + normalised Laplacian and the multi-scale extrema, spread
+    over `nlanes` internal streams.  Owns the per-frame outputs and the
+    workspace, so run() allocates nothing and can be captured into a graph
+    (torch.cuda.graph) and replayed.  row_chunks: per frame 0 (default) or the
+    row-pass samples per lane (8, 16, 32), e.g. from autotune_batch()."""
+
+    def __init__(self, frames, sigmas: Sequence[float], tau: float, order: int = 3, boundary: str = "replicate",
+                 border: int = 1, nlanes: int = 4, cap: int = 1 << 16, row_chunks=None):
+        torch = _torch()
+        self.frames = [_frame(f) for f in frames]
+        dev = self.frames[0].device
+        n = len(self.frames)
+        self.sigmas = list(sigmas)
+        self.filters = iir_designs(self.sigmas, order)
+        self.tau, self.border, self.boundary = float(tau), int(border), boundary
+        self.nlanes = int(max(1, min(nlanes, MAX_LANES)))
+        self.cap = int(cap)
+        self.out = torch.empty((n, max(self.cap, 1) * BLOB_BYTES), dtype=torch.uint8, device=dev)
+        self.counts = torch.zeros(n, dtype=torch.int32, device=dev)
+        self.desc = (Frame * n)()
+        chunks = row_chunks if row_chunks is not None else [0] * n
+        for i, f in enumerate(self.frames):
+            H, W = f.shape
+            self.desc[i] = Frame(f.data_ptr(), _dtype_code(f), H, W, int(chunks[i]), f.stride(0),
+                                 self.out[i].data_ptr(), self.counts[i:].data_ptr(), self.cap, 0)
+        need = int(lib().fdvm_batch_workspace_bytes(self.desc, n, len(self.sigmas), self.nlanes))
+        if need == 0:
+            raise FdvmError(EINVAL, "fdvm_batch_workspace_bytes")
+        self.ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        self.device = dev
+
+    def run(self):
+        """Enqueue the batch on the current stream (asynchronous)."""
+        _check(lib().fdvm_batch_detect(self.desc, len(self.frames), self.filters, len(self.sigmas),
+                                       BOUNDARIES[self.boundary], self.tau, self.border, self.nlanes,
+                                       self.ws.data_ptr(), self.ws.numel(), _stream_ptr(self.device)),
+               "fdvm_batch_detect")
+
+    def results(self):
+        """Per frame, the blob list as a structured numpy array (synchronises)."""
+        counts = self.counts.cpu().numpy()
+        out = []
+        for i, n in enumerate(counts):
+            if n > self.cap:
+                raise FdvmError(EOVERFLOW, f"frame {i}: {n} detections > cap {self.cap}")
+            raw = self.out[i, : int(n) * BLOB_BYTES].cpu().numpy()
+            out.append(raw.view(BLOB_DTYPE).copy())
+        return out
+
+
+def row_chunk_choices(W: int):
+    """Row-pass samples per lane that can cover a row of W samples."""
+    return [c for c in (8, 16, 32) if W <= 8 * 64 * c]
+
+
+def autotune_batch(frames, sigmas: Sequence[float], tau: float, lanes=(1, 2, 4, 8), reps: int = 3, **kw):
+    """Pick the lane count and, per distinct frame width, the row-pass chunk by
+    timing the batch on the device.  Returns (nlanes, row_chunks, timings)."""
+    torch = _torch()
+    frames = [_frame(f) for f in frames]
+    widths = sorted({int(f.shape[1]) for f in frames})
+
+    def time_batch(nl, chunk_of):
+        b = Batch(frames, sigmas, tau, nlanes=nl, row_chunks=[chunk_of[int(f.shape[1])] for f in frames], **kw)
+        b.run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.run()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    chunk_of = {w: 0 for w in widths}
+    timings = {}
+    best_nl, best_t = None, None
+    for nl in lanes:
+        t = time_batch(nl, chunk_of)
+        timings[("lanes", nl)] = t
+        if best_t is None or t < best_t:
+            best_nl, best_t = nl, t
+    for w in widths:   # one width at a time, the others at their current choice
+        for c in row_chunk_choices(w):
+            trial = dict(chunk_of)
+            trial[w] = c
+            t = time_batch(best_nl, trial)
+            timings[("chunk", w, c)] = t
+            if t < best_t:
+                best_t, chunk_of = t, trial
+    return best_nl, [chunk_of[int(f.shape[1])] for f in frames], timings
+
+
 def scale_of(sigma: float) -> float:
     """Blob scale lambda = 2 sigma (Section 5)."""
     return 2.0 * sigma
 
 
 __all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "iir_laplacian", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
-           "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of"]
+           "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of",
+           "Batch", "autotune_batch", "row_chunk_choices", "Frame"]
 _ = math

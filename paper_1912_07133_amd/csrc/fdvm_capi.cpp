@@ -1,7 +1,10 @@
 // C ABI of the blob-detection filter bank: argument validation on the host,
 // then dispatch to the HIP kernels.  See include/fdvm.h for the contract.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "fdvm_internal.h"
 
@@ -157,7 +160,7 @@ fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     hipStream_t hs = static_cast<hipStream_t>(stream);
     if (axis == 0) {
         if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
-        return from_hip(launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, nullptr, prm, hs));
+        return from_hip(launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, nullptr, 0, prm, hs));
     }
     if (axis == 1 || axis == 2) {
         if (dt != FDVM_F32) return FDVM_EINVAL;
@@ -192,7 +195,7 @@ fdvm_status fdvm_blur_iir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     hipStream_t hs = static_cast<hipStream_t>(stream);
     // the fixed-point intermediate lives in `out` and is replaced in place
     int *rexp = reinterpret_cast<int *>(static_cast<char *>(ws) + st_bytes);
-    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, hs);
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, rexp, 0, prm, hs);
     if (e != hipSuccess) return FDVM_EDEVICE;
     return from_hip(launch_iir_cols(out, out_pitch, plane_stride, rexp, out, H, W, out_pitch, plane_stride, false,
                                     prm, ws, hs));
@@ -221,7 +224,7 @@ fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
     const int64_t rstride = (int64_t)(plane_bytes / sizeof(int32_t));
     void *states = static_cast<char *>(ws) + plane_bytes * nscales;
     int *rexp = reinterpret_cast<int *>(static_cast<char *>(states) + st_bytes);
-    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, rows, W, rstride, rexp, prm, hs);
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, rows, W, rstride, rexp, 0, prm, hs);
     if (e != hipSuccess) return FDVM_EDEVICE;
     return from_hip(
         launch_iir_cols(rows, W, rstride, rexp, out, H, W, out_pitch, plane_stride, true, prm, states, hs));
@@ -293,6 +296,137 @@ fdvm_status fdvm_detect_blobs(const float *resp, int64_t H, int64_t W, int64_t p
     hipError_t e = launch_detect(resp, H, W, pitch, plane_stride, nscales, tau, border, out_dev, cap, count_dev,
                                  ws, static_cast<hipStream_t>(stream));
     return from_hip(e);
+}
+
+
+}  // extern "C"
+
+namespace {
+
+// internal streams and events of the batch lanes, created once per device
+struct Lanes {
+    int device = -1;
+    hipStream_t st[FDVM_MAX_LANES] = {};
+    hipEvent_t done[FDVM_MAX_LANES] = {};
+    hipEvent_t fork = nullptr;
+};
+std::mutex g_lanes_mu;
+std::vector<Lanes *> g_lanes;
+
+Lanes *lanes_for_current_device() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(g_lanes_mu);
+    for (Lanes *l : g_lanes)
+        if (l->device == dev) return l;
+    Lanes *l = new Lanes();
+    l->device = dev;
+    // default priority, non-blocking with respect to the null stream
+    for (int i = 0; i < FDVM_MAX_LANES; ++i)
+        if (hipStreamCreateWithFlags(&l->st[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&l->done[i], hipEventDisableTiming) != hipSuccess)
+            return nullptr;
+    if (hipEventCreateWithFlags(&l->fork, hipEventDisableTiming) != hipSuccess) return nullptr;
+    g_lanes.push_back(l);
+    return l;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// per-lane workspace, sized for the largest frame term by term
+struct LaneLayout {
+    size_t mid = 0, states = 0, rexp = 0, vplanes = 0, det = 0;
+    size_t total() const { return mid + states + rexp + vplanes + det; }
+};
+LaneLayout lane_layout(const fdvm_frame *frames, int nframes, int nscales, int order) {
+    LaneLayout L;
+    for (int f = 0; f < nframes; ++f) {
+        const int64_t H = frames[f].H, W = frames[f].W;
+        const size_t plane = round256((size_t)H * W * sizeof(int32_t));
+        L.mid = std::max(L.mid, plane * nscales);
+        L.states = std::max(L.states, iir_cols_workspace_bytes(H, W, nscales, order));
+        L.rexp = std::max(L.rexp, iir_rexp_bytes(H));
+        L.vplanes = std::max(L.vplanes, round256((size_t)H * W * sizeof(float) * nscales));
+        L.det = std::max(L.det, detect_workspace_bytes(H, W, nscales));
+    }
+    return L;
+}
+
+fdvm_status check_frame(const fdvm_frame &f) {
+    if (!f.data || !f.out || !f.count || f.cap < 0) return FDVM_EINVAL;
+    if (f.H < 1 || f.W < 1 || f.H > 65535 || f.W > 16384 || f.pitch < f.W) return FDVM_EINVAL;
+    if (check_dtype((fdvm_dtype)f.dtype) != FDVM_OK) return FDVM_EINVAL;
+    if (f.row_chunk != 0 && f.row_chunk != 8 && f.row_chunk != 16 && f.row_chunk != 32) return FDVM_EINVAL;
+    const int64_t chunk = f.row_chunk ? f.row_chunk : 32;
+    if (f.W > 8 * 64 * chunk) return FDVM_EUNSUPPORTED;
+    return FDVM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fdvm_batch_workspace_bytes(const fdvm_frame *frames, int nframes, int nscales, int nlanes) {
+    if (!frames || nframes < 1 || nscales < 1 || nscales > FDVM_MAX_SCALES || nlanes < 1 ||
+        nlanes > FDVM_MAX_LANES)
+        return 0;
+    for (int f = 0; f < nframes; ++f)
+        if (frames[f].H < 1 || frames[f].W < 1) return 0;
+    return lane_layout(frames, nframes, nscales, 3).total() * (size_t)std::min(nlanes, nframes);
+}
+
+fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_filter *filters, int nscales,
+                              fdvm_boundary bc, float tau, int border, int nlanes, void *ws, size_t ws_bytes,
+                              void *stream) {
+    if (!frames || nframes < 1 || !ws) return FDVM_EINVAL;
+    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
+    if (nlanes < 1 || nlanes > FDVM_MAX_LANES) return FDVM_EINVAL;
+    if (!(tau >= 0.0f) || !std::isfinite(tau) || border < 0) return FDVM_EINVAL;
+    for (int f = 0; f < nframes; ++f) {
+        const fdvm_status st = check_frame(frames[f]);
+        if (st != FDVM_OK) return st;
+    }
+    IirParams prm;
+    fdvm_status st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
+    const LaneLayout L = lane_layout(frames, nframes, nscales, prm.order);
+    const int used = std::min(nlanes, nframes);
+    if (ws_bytes < L.total() * (size_t)used) return FDVM_ENOMEM;
+    hipStream_t origin = static_cast<hipStream_t>(stream);
+    Lanes *lanes = nullptr;
+    if (used > 1) {
+        lanes = lanes_for_current_device();
+        if (!lanes) return FDVM_EDEVICE;
+        if (hipEventRecord(lanes->fork, origin) != hipSuccess) return FDVM_EDEVICE;
+        for (int l = 0; l < used; ++l)
+            if (hipStreamWaitEvent(lanes->st[l], lanes->fork, 0) != hipSuccess) return FDVM_EDEVICE;
+    }
+    for (int f = 0; f < nframes; ++f) {
+        const fdvm_frame &fr = frames[f];
+        const int l = f % used;
+        hipStream_t hs = used > 1 ? lanes->st[l] : origin;
+        char *base = static_cast<char *>(ws) + L.total() * (size_t)l;
+        const int64_t H = fr.H, W = fr.W;
+        int32_t *mid = reinterpret_cast<int32_t *>(base);
+        const int64_t mstride = (int64_t)(round256((size_t)H * W * sizeof(int32_t)) / sizeof(int32_t));
+        void *states = base + L.mid;
+        int *rexp = reinterpret_cast<int *>(base + L.mid + L.states);
+        float *V = reinterpret_cast<float *>(base + L.mid + L.states + L.rexp);
+        void *det = base + L.mid + L.states + L.rexp + L.vplanes;
+        hipError_t e = launch_iir_rows(fr.data, fr.dtype, H, W, fr.pitch, mid, W, mstride, rexp, fr.row_chunk, prm, hs);
+        if (e == hipSuccess)
+            e = launch_iir_cols(mid, W, mstride, rexp, V, H, W, W, H * W, true, prm, states, hs);
+        if (e == hipSuccess)
+            e = launch_detect(V, H, W, W, H * W, nscales, tau, border, fr.out, fr.cap, fr.count, det, hs);
+        if (e != hipSuccess) return FDVM_EDEVICE;
+    }
+    if (used > 1) {
+        for (int l = 0; l < used; ++l) {
+            if (hipEventRecord(lanes->done[l], lanes->st[l]) != hipSuccess) return FDVM_EDEVICE;
+            if (hipStreamWaitEvent(origin, lanes->done[l], 0) != hipSuccess) return FDVM_EDEVICE;
+        }
+    }
+    return FDVM_OK;
 }
 
 }  // extern "C"

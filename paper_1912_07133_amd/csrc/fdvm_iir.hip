@@ -758,36 +758,61 @@ Args make_args(const IirParams &prm, int C) {
     return a;
 }
 
-template <int K, int C, int R, typename T>
+template <int K, int C, int R, typename T, bool FX>
 hipError_t launch_rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, void *out, int64_t out_pitch,
                          int64_t plane_stride, int *rexp, const IirParams &prm, hipStream_t st) {
     Args a = make_args(prm, C);
     const int rows_per_block = ROW_WPB / R;
     dim3 grid((unsigned)((H + rows_per_block - 1) / rows_per_block));
-    if (rexp)
-        hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T, true>), grid, dim3(ROW_WPB * 64), 0, st,
-                           static_cast<const T *>(in), in_pitch, out, out_pitch, plane_stride, (int)H, (int)W,
-                           rexp, a);
-    else
-        hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T, false>), grid, dim3(ROW_WPB * 64), 0, st,
-                           static_cast<const T *>(in), in_pitch, out, out_pitch, plane_stride, (int)H, (int)W,
-                           rexp, a);
+    hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T, FX>), grid, dim3(ROW_WPB * 64), 0, st,
+                       static_cast<const T *>(in), in_pitch, out, out_pitch, plane_stride, (int)H, (int)W, rexp, a);
     return hipGetLastError();
 }
 
+// chunk length C per lane and wavefronts per row R with 64 C R >= W,
+// R in {1, 2, 4, 8}: by default the smallest C in {8, 16, 32} (R = 1) or
+// C = 32 with the smallest R; with chunk = 8, 16 or 32 (fixed-point
+// intermediate only) that C with the smallest R
 template <int K, typename T>
 hipError_t launch_rows_k(const void *in, int64_t H, int64_t W, int64_t in_pitch, void *out, int64_t out_pitch,
-                         int64_t plane_stride, int *rexp, const IirParams &prm, hipStream_t st) {
-    // chunk length C per lane and wavefronts per row R: smallest C in
-    // {8, 16, 32} with 64 C R >= W, R in {1, 2, 4, 8}
-#define FDVM_ROWS_CR(CC, RR) \
-    return launch_rows_t<K, CC, RR, T>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st)
-    if (W <= 64 * 8) FDVM_ROWS_CR(8, 1);
-    if (W <= 64 * 16) FDVM_ROWS_CR(16, 1);
-    if (W <= 64 * 32) FDVM_ROWS_CR(32, 1);
-    if (W <= 2 * 64 * 32) FDVM_ROWS_CR(32, 2);
-    if (W <= 4 * 64 * 32) FDVM_ROWS_CR(32, 4);
-    if (W <= 8 * 64 * 32) FDVM_ROWS_CR(32, 8);
+                         int64_t plane_stride, int *rexp, int chunk, const IirParams &prm, hipStream_t st) {
+#define FDVM_ROWS_CR(CC, RR, FXV)                                                                       \
+    return launch_rows_t<K, CC, RR, T, FXV>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st)
+    if (rexp && chunk != 0) {
+        const int64_t need = (W + 64 * chunk - 1) / (64 * chunk);  // wavefronts per row
+        if (chunk == 8) {
+            if (need <= 1) FDVM_ROWS_CR(8, 1, true);
+            if (need <= 2) FDVM_ROWS_CR(8, 2, true);
+            if (need <= 4) FDVM_ROWS_CR(8, 4, true);
+            if (need <= 8) FDVM_ROWS_CR(8, 8, true);
+        } else if (chunk == 16) {
+            if (need <= 1) FDVM_ROWS_CR(16, 1, true);
+            if (need <= 2) FDVM_ROWS_CR(16, 2, true);
+            if (need <= 4) FDVM_ROWS_CR(16, 4, true);
+            if (need <= 8) FDVM_ROWS_CR(16, 8, true);
+        } else if (chunk == 32) {
+            if (need <= 1) FDVM_ROWS_CR(32, 1, true);
+            if (need <= 2) FDVM_ROWS_CR(32, 2, true);
+            if (need <= 4) FDVM_ROWS_CR(32, 4, true);
+            if (need <= 8) FDVM_ROWS_CR(32, 8, true);
+        }
+        return hipErrorInvalidValue;
+    }
+    if (rexp) {
+        if (W <= 64 * 8) FDVM_ROWS_CR(8, 1, true);
+        if (W <= 64 * 16) FDVM_ROWS_CR(16, 1, true);
+        if (W <= 64 * 32) FDVM_ROWS_CR(32, 1, true);
+        if (W <= 2 * 64 * 32) FDVM_ROWS_CR(32, 2, true);
+        if (W <= 4 * 64 * 32) FDVM_ROWS_CR(32, 4, true);
+        if (W <= 8 * 64 * 32) FDVM_ROWS_CR(32, 8, true);
+    } else {
+        if (W <= 64 * 8) FDVM_ROWS_CR(8, 1, false);
+        if (W <= 64 * 16) FDVM_ROWS_CR(16, 1, false);
+        if (W <= 64 * 32) FDVM_ROWS_CR(32, 1, false);
+        if (W <= 2 * 64 * 32) FDVM_ROWS_CR(32, 2, false);
+        if (W <= 4 * 64 * 32) FDVM_ROWS_CR(32, 4, false);
+        if (W <= 8 * 64 * 32) FDVM_ROWS_CR(32, 8, false);
+    }
 #undef FDVM_ROWS_CR
     return hipErrorInvalidValue;
 }
@@ -836,18 +861,18 @@ hipError_t launch_cols_k(const void *in, int64_t in_pitch, int64_t in_plane_stri
 }  // namespace
 
 hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, void *out,
-                           int64_t out_pitch, int64_t plane_stride, int *rexp, const IirParams &prm,
+                           int64_t out_pitch, int64_t plane_stride, int *rexp, int chunk, const IirParams &prm,
                            hipStream_t st) {
 #define FDVM_ROWS_DT(KK)                                                                                    \
     switch (dtype) {                                                                                        \
         case FDVM_U16:                                                                                      \
-            return launch_rows_k<KK, uint16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st); \
+            return launch_rows_k<KK, uint16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, chunk, prm, st); \
         case FDVM_F32:                                                                                      \
-            return launch_rows_k<KK, float>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st);    \
+            return launch_rows_k<KK, float>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, chunk, prm, st);    \
         case FDVM_F16:                                                                                      \
-            return launch_rows_k<KK, _Float16>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st); \
+            return launch_rows_k<KK, _Float16>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, chunk, prm, st); \
         case FDVM_BF16:                                                                                     \
-            return launch_rows_k<KK, bf16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, prm, st);   \
+            return launch_rows_k<KK, bf16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, rexp, chunk, prm, st);   \
         default: return hipErrorInvalidValue;                                                               \
     }
     if (prm.order == 3) { FDVM_ROWS_DT(3) }

@@ -53,9 +53,10 @@ struct IirParams {
 
 // Row pass.  rexp == nullptr: `out` receives float32 planes.  Otherwise `out`
 // receives the int32 fixed-point intermediate and rexp[y] the exponent of row y
-// (sample = q 2^-rexp[y]).
+// (sample = q 2^-rexp[y]); then chunk (8, 16 or 32; 0 = from W) sets the
+// samples per lane.
 hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
-                           void *out, int64_t out_pitch, int64_t plane_stride, int *rexp,
+                           void *out, int64_t out_pitch, int64_t plane_stride, int *rexp, int chunk,
                            const IirParams &prm, hipStream_t stream);
 size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order);
 inline size_t iir_rexp_bytes(int64_t H) { return ((size_t)H * sizeof(int) + 255) & ~(size_t)255; }

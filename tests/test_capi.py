@@ -132,3 +132,43 @@ def test_workspace_sizes():
     assert P.workspace_bytes(P.OP_IIR_LAPLACIAN, 2048, 2048, 8) >= 8 * 2048 * 2048 * 4
     assert P.workspace_bytes(P.OP_BLUR_FIR, 2048, 2048, 8, 192) >= 2048 * 2048 * 4
     assert P.workspace_bytes(P.OP_DETECT, 2048, 2048, 8) >= 8 * 2048 * (2048 // 64) * 8
+
+
+def test_batch_layout_and_validation():
+    """fdvm_frame layout, batch workspace sizing, and host-side rejection of bad
+    batches (fake device pointers, nothing is launched)."""
+    assert ctypes.sizeof(P.Frame) == 56
+    L = P.lib()
+    f = P.Filter()
+    assert L.fdvm_filter_design(0, 3, 4.0, 0, ctypes.byref(f), None, 0) == P.OK
+    filt = (P.Filter * 2)(f, f)
+    fake = 0x1000
+
+    def frames(*shapes, chunk=0, dtype=P.U16):
+        fr = (P.Frame * len(shapes))()
+        for i, (H, W) in enumerate(shapes):
+            fr[i] = P.Frame(fake, dtype, H, W, chunk, W, fake, fake, 16, 0)
+        return fr
+
+    two = frames((300, 500), (64, 2048))
+    per_lane = L.fdvm_batch_workspace_bytes(two, 2, 2, 1)
+    # the largest frame term by term: x-pass planes + V planes of the 300 x 500
+    # frame, states and words of the wider one
+    assert per_lane >= 2 * (300 * 500 * 4) * 2
+    assert L.fdvm_batch_workspace_bytes(two, 2, 2, 2) == 2 * per_lane
+    assert L.fdvm_batch_workspace_bytes(two, 2, 2, 8) == 2 * per_lane   # lanes capped at the frame count
+    assert L.fdvm_batch_workspace_bytes(two, 2, 17, 1) == 0
+    ws = ctypes.c_void_p(fake)
+    big = 1 << 40
+    ok = lambda fr, n=2, lanes=2, tau=1.0: L.fdvm_batch_detect(fr, n, filt, 2, 0, tau, 1, lanes, ws, big, None)
+    assert ok(frames((0, 5), (4, 4))) == P.EINVAL
+    assert ok(frames((5, 5), (4, 4), chunk=12)) == P.EINVAL
+    assert ok(frames((5, 5), (4, 4), dtype=9)) == P.EINVAL
+    assert ok(frames((5, 5), (4, 16384), chunk=8)) == P.EUNSUPPORTED   # 64 * 8 * 8 < 16384
+    assert ok(frames((5, 5), (4, 4)), lanes=0) == P.EINVAL
+    assert ok(frames((5, 5), (4, 4)), lanes=17) == P.EINVAL
+    assert ok(frames((5, 5), (4, 4)), tau=-1.0) == P.EINVAL
+    bad = frames((5, 5), (4, 4))
+    bad[1].pitch = 3
+    assert ok(bad) == P.EINVAL
+    assert L.fdvm_batch_detect(two, 2, filt, 2, 0, 1.0, 1, 2, ws, 16, None) == P.ENOMEM
