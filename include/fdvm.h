@@ -58,6 +58,8 @@ typedef enum {
 
 typedef enum {
     FDVM_IIR_REPEATED_POLE = 0, /* Filter D, Section 4.3 (order K = 2 or 3)   */
+    FDVM_IIR_REPEATED_POLE_DSIGMA = 3, /* d h / d sigma of that blur (K + 1
+                                    cascade sections); fdvm_iir_pass only   */
     FDVM_FIR_COLORED_SG = 1,    /* Filter C, Section 4.2 (Eqs 20-22)          */
     FDVM_FIR_GAUSSIAN = 2       /* Filter A, Eqs 9c and 11                    */
 } fdvm_kind;
@@ -123,6 +125,12 @@ const char *fdvm_status_string(fdvm_status status);
  *     with one Nyquist constraint (unit dc gain, zero second moment,
  *     H(pi) = 0).  sigma in [0.25, 4096].  `fir_half_len`, `taps`,
  *     `taps_cap` are ignored (taps may be NULL).
+ *   kind = FDVM_IIR_REPEATED_POLE_DSIGMA: the derivative d h / d sigma of the
+ *     order-K blur at sigma (p = exp(-1/sigma), dp/dsigma = p / sigma^2); b0
+ *     receives d h(0) / d sigma.  Realised as K + 1 cascade sections with the
+ *     same pole (a k-fold section differentiates into sections k and k + 1).
+ *     Usable in fdvm_iir_pass (axes 0 and 1); with the replicate extension the
+ *     pass is the sigma derivative of the blur pass of the extended input.
  *   kind = FDVM_FIR_COLORED_SG: Eq 20 solved in float64 with S from Eq 22,
  *     omega_c = 3/sigma and dc constraints rho = [1, 0] (D = 3); needs
  *     omega_c < pi (sigma > 3/pi), otherwise the stopband of Eq 21 is empty
@@ -229,8 +237,48 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
                           int nscales, fdvm_boundary bc, int algo,
                           void *ws, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------------------ adjoints
+ * Transposed operators for gradients (the paper's filters are linear; these
+ * are the exact transposes of the float64-defined operators).
+ *
+ * fdvm_blur_iir_adjoint -- out_s = G_s^T g_s for the separable repeated-pole
+ *   blur G_s of fdvm_blur_iir (rows then columns, extension bc): the
+ *   zero-start recursions along columns then rows (h is symmetric), and, for
+ *   the replicate extension, the tails that the transposed extension folds
+ *   back onto the first and last sample of every column and row,
+ *   sum_m g(m) T(m) with T(m) = sum_{k>m} h(k).
+ *   g, out: device float32 planes (pitch, plane stride as in fdvm_blur_iir;
+ *   must not overlap).  filters: FDVM_IIR_REPEATED_POLE designs.  ws: device,
+ *   >= fdvm_workspace_bytes(FDVM_OP_BLUR_IIR_ADJOINT, H, W, nscales, 0).
+ */
+fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                                  float *out, int64_t out_pitch, int64_t out_plane_stride,
+                                  const fdvm_filter *filters, int nscales, fdvm_boundary bc, void *ws,
+                                  size_t ws_bytes, void *stream);
+
+/*
+ * fdvm_laplacian_adjoint -- out_s = sigma_s^2 Lap^T g_s, the transpose of the
+ *   normalised Laplacian of fdvm_highpass(FDVM_HP_LAPLACIAN, normalize = 1)
+ *   (Table I d = 2 taps along x and y, clamp-to-edge extension).
+ *   g, out: device float32 planes, must not overlap.
+ */
+fdvm_status fdvm_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                                   int nscales, const double *sigmas, float *out, int64_t out_pitch,
+                                   int64_t out_plane_stride, void *stream);
+
+/*
+ * fdvm_plane_dots -- out_dev[s] = sum_{y,x} a_s(y, x) b_s(y, x) in float64,
+ *   summed in a fixed order (the same result on every run).  a, b: device
+ *   float32 planes with the same pitch and plane stride.  ws: device,
+ *   >= fdvm_workspace_bytes(FDVM_OP_PLANE_DOTS, H, W, nscales, 0).
+ */
+fdvm_status fdvm_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch,
+                            int64_t plane_stride, int nscales, double *out_dev, void *ws, size_t ws_bytes,
+                            void *stream);
+
 /* workspace sizes */
-enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3 };
+enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3,
+       FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5 };
 
 /* Bytes of device workspace `op` needs for an H x W frame with nscales
  * scales and maximum FIR half-length max_half_len (0 if unused). */

@@ -24,12 +24,12 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "fdvm.h")
 
 # enums (include/fdvm.h)
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EOVERFLOW, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN = 0, 1, 2
+IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN, IIR_REPEATED_POLE_DSIGMA = 0, 1, 2, 3
 BC_REPLICATE, BC_ZERO = 0, 1
 U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
-OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN = 0, 1, 2, 3
+OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS = 0, 1, 2, 3, 4, 5
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
 
@@ -111,6 +111,14 @@ def lib() -> ctypes.CDLL:
         L.fdvm_detect_blobs.restype = ctypes.c_int
         L.fdvm_detect_blobs.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_float,
                                         ctypes.c_int, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.fdvm_blur_iir_adjoint.restype = ctypes.c_int
+        L.fdvm_blur_iir_adjoint.argtypes = [vp, i64, i64, i64, i64, vp, i64, i64, ctypes.POINTER(Filter),
+                                            ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
+        L.fdvm_laplacian_adjoint.restype = ctypes.c_int
+        L.fdvm_laplacian_adjoint.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.POINTER(dbl), vp, i64,
+                                             i64, vp]
+        L.fdvm_plane_dots.restype = ctypes.c_int
+        L.fdvm_plane_dots.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, vp, vp, ctypes.c_size_t, vp]
         L.fdvm_batch_workspace_bytes.restype = ctypes.c_size_t
         L.fdvm_batch_workspace_bytes.argtypes = [ctypes.POINTER(Frame), ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.fdvm_batch_detect.restype = ctypes.c_int
@@ -240,24 +248,26 @@ def iir_laplacian(x, sigmas: Sequence[float], order: int = 3, boundary: str = "r
     return out
 
 
-def iir_designs(sigmas: Sequence[float], order: int = 3):
-    """ctypes array of fdvm_filter designs, one per scale (fdvm_filter_design)."""
+def iir_designs(sigmas: Sequence[float], order: int = 3, dsigma: bool = False):
+    """ctypes array of fdvm_filter designs, one per scale (fdvm_filter_design);
+    dsigma: the sigma derivatives of the blurs instead."""
+    kind = IIR_REPEATED_POLE_DSIGMA if dsigma else IIR_REPEATED_POLE
     filt = (Filter * len(sigmas))()
     for i, s in enumerate(sigmas):
-        _check(lib().fdvm_filter_design(IIR_REPEATED_POLE, order, float(s), 0, ctypes.byref(filt[i]), None, 0),
+        _check(lib().fdvm_filter_design(kind, order, float(s), 0, ctypes.byref(filt[i]), None, 0),
                "fdvm_filter_design")
     return filt
 
 
 def iir_pass(x, sigmas: Sequence[float], axis: int, order: int = 3, boundary: str = "replicate", out=None,
-             workspace=None):
+             workspace=None, dsigma: bool = False):
     """One pass of the IIR blur (fdvm_iir_pass).  axis 0: frame [H, W] ->
     [S, H, W] filtered along x; axis 1: planes [S, H, W] (float32) filtered
     along y (out may be the input itself); axis 2: as 1, then the normalised
-    Laplacian."""
+    Laplacian.  dsigma (axes 0, 1): apply d h / d sigma instead of h."""
     torch = _torch()
     S = len(sigmas)
-    filt = iir_designs(sigmas, order)
+    filt = iir_designs(sigmas, order, dsigma)
     if axis == 0:
         x = _frame(x)
         H, W = x.shape
@@ -377,6 +387,119 @@ def detect(frame, sigmas: Sequence[float], tau: float, kind: str = "iir", order:
     return detect_blobs(V, tau, border, cap), V
 
 
+# ------------------------------------------------------------------ gradients
+def _planes(t):
+    torch = _torch()
+    if t.dtype != torch.float32 or t.dim() != 3 or t.stride(2) != 1:
+        raise ValueError("expected float32 planes [S, H, W] with unit x stride")
+    return t
+
+
+def blur_iir_adjoint(g, sigmas: Sequence[float], order: int = 3, boundary: str = "replicate", out=None):
+    """fdvm_blur_iir_adjoint: planes [S, H, W] -> G_s^T g_s, the transpose of
+    the replicate (or zero) extension blur of blur_iir."""
+    torch = _torch()
+    g = _planes(g.contiguous())
+    S, H, W = g.shape
+    if out is None:
+        out = torch.empty_like(g)
+    filt = iir_designs(sigmas, order)
+    ws = _workspace(OP_BLUR_IIR_ADJOINT, H, W, S, g.device)
+    _check(lib().fdvm_blur_iir_adjoint(g.data_ptr(), H, W, g.stride(1), g.stride(0), out.data_ptr(), out.stride(1),
+                                       out.stride(0), filt, S, BOUNDARIES[boundary], ws.data_ptr(), ws.numel(),
+                                       _stream_ptr(g.device)), "fdvm_blur_iir_adjoint")
+    return out
+
+
+def laplacian_adjoint(g, sigmas: Sequence[float], out=None):
+    """fdvm_laplacian_adjoint: planes [S, H, W] -> sigma_s^2 Lap^T g_s."""
+    torch = _torch()
+    g = _planes(g.contiguous())
+    S, H, W = g.shape
+    if out is None:
+        out = torch.empty_like(g)
+    sig = (ctypes.c_double * S)(*[float(x) for x in sigmas])
+    _check(lib().fdvm_laplacian_adjoint(g.data_ptr(), H, W, g.stride(1), g.stride(0), S, sig, out.data_ptr(),
+                                        out.stride(1), out.stride(0), _stream_ptr(g.device)), "fdvm_laplacian_adjoint")
+    return out
+
+
+def plane_dots(a, b):
+    """fdvm_plane_dots: per-plane float64 inner products of two [S, H, W]
+    float32 stacks with the same layout -> float64 device tensor [S]."""
+    torch = _torch()
+    a = _planes(a.contiguous())
+    b = _planes(b.contiguous())
+    if a.shape != b.shape:
+        raise ValueError("shapes differ")
+    S, H, W = a.shape
+    out = torch.empty(S, dtype=torch.float64, device=a.device)
+    ws = _workspace(OP_PLANE_DOTS, H, W, S, a.device)
+    _check(lib().fdvm_plane_dots(a.data_ptr(), b.data_ptr(), H, W, a.stride(1), a.stride(0), S, out.data_ptr(),
+                                 ws.data_ptr(), ws.numel(), _stream_ptr(a.device)), "fdvm_plane_dots")
+    return out
+
+
+def dblur_dsigma_parts(x, sigmas: Sequence[float], order: int = 3, boundary: str = "replicate"):
+    """d B_s / d sigma_s of blur_iir as two stacks whose sum it is:
+    (d/dsigma along x, blur along y) and (blur along x, d/dsigma along y)."""
+    R = iir_pass(x, sigmas, 0, order, boundary)
+    Rd = iir_pass(x, sigmas, 0, order, boundary, dsigma=True)
+    D1 = iir_pass(Rd, sigmas, 1, order, boundary, out=Rd)
+    D2 = iir_pass(R, sigmas, 1, order, boundary, out=R, dsigma=True)
+    return D1, D2
+
+
+def _make_iir_laplacian_fn():
+    torch = _torch()
+
+    class IirLaplacianFn(torch.autograd.Function):
+        """V_s = sigma_s^2 (D20 + D02)(B_s), B_s the repeated-pole blur of x
+        (iir_laplacian), differentiable in x (float32 frame [H, W]) and sigma
+        (float64 tensor [S]) through hand-written adjoint kernels:
+            dL/dB_s     = sigma_s^2 Lap^T dL/dV_s          (laplacian_adjoint)
+            dL/dx       = sum_s G_s^T dL/dB_s              (blur_iir_adjoint)
+            dL/dsigma_s = 2/sigma_s <dL/dV_s, V_s> + <dL/dB_s, dB_s/dsigma_s>
+        with dB_s/dsigma_s from the sigma-derivative recursions."""
+
+        @staticmethod
+        def forward(ctx, x, sigma, order=3, boundary="replicate"):
+            sig = [float(v) for v in sigma.detach().cpu().tolist()]
+            V = iir_laplacian(x.detach(), sig, order=order, boundary=boundary)
+            ctx.save_for_backward(x, V)
+            ctx.sig, ctx.order, ctx.boundary = sig, order, boundary
+            return V
+
+        @staticmethod
+        def backward(ctx, gV):
+            x, V = ctx.saved_tensors
+            sig = ctx.sig
+            gV = gV.contiguous().float()
+            gB = laplacian_adjoint(gV, sig)
+            gx = gsig = None
+            if ctx.needs_input_grad[0]:
+                gx = blur_iir_adjoint(gB, sig, ctx.order, ctx.boundary).sum(0)
+            if ctx.needs_input_grad[1]:
+                D1, D2 = dblur_dsigma_parts(x.detach(), sig, ctx.order, ctx.boundary)
+                s = torch.tensor(sig, dtype=torch.float64, device=V.device)
+                gsig = 2.0 / s * plane_dots(gV, V) + plane_dots(gB, D1) + plane_dots(gB, D2)
+            return gx, gsig, None, None
+
+    return IirLaplacianFn
+
+
+_iir_lap_fn = None
+
+
+def iir_laplacian_grad(x, sigma, order: int = 3, boundary: str = "replicate"):
+    """Differentiable iir_laplacian: x float32 [H, W] (requires_grad allowed),
+    sigma float64 tensor [S] (requires_grad allowed) -> V [S, H, W]."""
+    global _iir_lap_fn
+    if _iir_lap_fn is None:
+        _iir_lap_fn = _make_iir_laplacian_fn()
+    return _iir_lap_fn.apply(x, sigma, order, boundary)
+
+
 # ------------------------------------------------------------------ batch
 class Batch:
     """Many frames of uneven size through fdvm_batch_detect: per frame the
@@ -480,5 +603,6 @@ def scale_of(sigma: float) -> float:
 
 __all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "iir_laplacian", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
            "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of",
-           "Batch", "autotune_batch", "row_chunk_choices", "Frame"]
+           "Batch", "autotune_batch", "row_chunk_choices", "Frame", "blur_iir_adjoint", "laplacian_adjoint",
+           "plane_dots", "dblur_dsigma_parts", "iir_laplacian_grad"]
 _ = math

@@ -58,6 +58,16 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
     std::memset(&f, 0, sizeof(f));
     f.kind = kind;
     f.sigma = sigma;
+    if (kind == FDVM_IIR_REPEATED_POLE_DSIGMA) {
+        if (order != 2 && order != 3) return FDVM_EINVAL;
+        if (!(sigma >= 0.25 && sigma <= 4096.0)) return FDVM_ERANGE;
+        const Cascade d = sigma_derivative_realisation(order, sigma);
+        f.order = order;
+        f.p = d.p;
+        f.b0 = d.b0;
+        *out = f;
+        return FDVM_OK;
+    }
     if (kind == FDVM_IIR_REPEATED_POLE) {
         if (order != 2 && order != 3) return FDVM_EINVAL;
         if (!(sigma >= 0.25 && sigma <= 4096.0)) return FDVM_ERANGE;
@@ -102,35 +112,46 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
 size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len) {
     if (H < 1 || W < 1 || nscales < 1) return 0;
     switch (op) {
-        case FDVM_OP_BLUR_IIR: return iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H);
+        case FDVM_OP_BLUR_IIR: return iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS) + iir_rexp_bytes(H);
         case FDVM_OP_IIR_LAPLACIAN:
             return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
                    iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H);
         case FDVM_OP_BLUR_FIR: return fir_workspace_bytes(H, W, nscales, max_half_len);
         case FDVM_OP_DETECT: return detect_workspace_bytes(H, W, nscales);
+        case FDVM_OP_BLUR_IIR_ADJOINT:
+            return (((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255) +
+                   iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS);
+        case FDVM_OP_PLANE_DOTS: return dots_workspace_bytes(H, nscales);
         default: return 0;
     }
 }
 
 namespace {
-fdvm_status iir_params(const fdvm_filter *filters, int nscales, fdvm_boundary bc, IirParams *prm) {
+// Realisations of the nscales designs: all of one kind (the blur, or with
+// allow_dsigma its sigma derivative) and one order.
+fdvm_status iir_params(const fdvm_filter *filters, int nscales, fdvm_boundary bc, IirParams *prm,
+                       bool allow_dsigma = false) {
     if (!filters) return FDVM_EINVAL;
     if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
     const int order = filters[0].order;
+    const int kind = filters[0].kind;
     if (order != 2 && order != 3) return FDVM_EINVAL;
+    if (kind != FDVM_IIR_REPEATED_POLE && !(allow_dsigma && kind == FDVM_IIR_REPEATED_POLE_DSIGMA))
+        return FDVM_EINVAL;
     std::memset(prm, 0, sizeof(*prm));
     prm->nscales = nscales;
-    prm->order = order;
     prm->boundary = bc;
     for (int s = 0; s < nscales; ++s) {
         const fdvm_filter &f = filters[s];
-        if (f.kind != FDVM_IIR_REPEATED_POLE || f.order != order) return FDVM_EINVAL;
+        if (f.kind != kind || f.order != order) return FDVM_EINVAL;
         if (!(f.sigma >= 0.25 && f.sigma <= 4096.0)) return FDVM_ERANGE;
-        const Cascade c = cascade_realisation(order, f.sigma);
+        const Cascade c = kind == FDVM_IIR_REPEATED_POLE ? cascade_realisation(order, f.sigma)
+                                                         : sigma_derivative_realisation(order, f.sigma);
+        prm->order = c.sections;
         IirScaleParams &q = prm->s[s];
         q.p = c.p;
         q.b0 = c.b0;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < MAX_SECTIONS; ++k) {
             q.w[k] = c.w[k];
             q.ss[k] = c.ss[k];
         }
@@ -155,7 +176,7 @@ fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     if (st != FDVM_OK) return st;
     if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
     IirParams prm;
-    st = iir_params(filters, nscales, bc, &prm);
+    st = iir_params(filters, nscales, bc, &prm, axis != 2);
     if (st != FDVM_OK) return st;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     if (axis == 0) {
@@ -228,6 +249,71 @@ fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
     if (e != hipSuccess) return FDVM_EDEVICE;
     return from_hip(
         launch_iir_cols(rows, W, rstride, rexp, out, H, W, out_pitch, plane_stride, true, prm, states, hs));
+}
+
+fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                                  float *out, int64_t out_pitch, int64_t out_plane_stride,
+                                  const fdvm_filter *filters, int nscales, fdvm_boundary bc, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(g, H, W, pitch);
+    if (st != FDVM_OK) return st;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    st = check_planes(out, H, W, out_pitch, out_plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (static_cast<const void *>(g) == static_cast<const void *>(out)) return FDVM_EINVAL;
+    IirParams prm;
+    st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
+    if (!ws) return FDVM_EINVAL;
+    const size_t ubytes = ((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255;
+    if (ws_bytes < ubytes + iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;
+    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    // G^T = (fold_x + zero-start x pass) (fold_y + zero-start y pass)
+    IirParams zp = prm;
+    zp.boundary = FDVM_BC_ZERO;
+    float *u = static_cast<float *>(ws);  // G_y^T g, pitch W
+    void *states = static_cast<char *>(ws) + ubytes;
+    hipError_t e = launch_iir_cols(g, pitch, plane_stride, nullptr, u, H, W, W, H * W, false, zp, states, hs);
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE) e = launch_fold(g, pitch, plane_stride, u, W, H * W, H, W, prm, 1, hs);
+    for (int s = 0; e == hipSuccess && s < nscales; ++s) {
+        IirParams one = zp;
+        one.nscales = 1;
+        one.s[0] = zp.s[s];
+        e = launch_iir_rows(u + (int64_t)s * H * W, FDVM_F32, H, W, W, out + (int64_t)s * out_plane_stride, out_pitch,
+                            out_plane_stride, nullptr, 0, one, hs);
+    }
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
+        e = launch_fold(u, W, H * W, out, out_pitch, out_plane_stride, H, W, prm, 0, hs);
+    return from_hip(e);
+}
+
+fdvm_status fdvm_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                                   int nscales, const double *sigmas, float *out, int64_t out_pitch,
+                                   int64_t out_plane_stride, void *stream) {
+    fdvm_status st = check_image(g, H, W, pitch);
+    if (st != FDVM_OK) return st;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    st = check_planes(out, H, W, out_pitch, out_plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (!sigmas || static_cast<const void *>(g) == static_cast<const void *>(out)) return FDVM_EINVAL;
+    for (int s = 0; s < nscales; ++s)
+        if (!finite_pos(sigmas[s])) return FDVM_ERANGE;
+    return from_hip(launch_laplacian_adjoint(g, H, W, pitch, plane_stride, nscales, sigmas, out, out_pitch,
+                                             out_plane_stride, static_cast<hipStream_t>(stream)));
+}
+
+fdvm_status fdvm_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch,
+                            int64_t plane_stride, int nscales, double *out_dev, void *ws, size_t ws_bytes,
+                            void *stream) {
+    fdvm_status st = check_image(a, H, W, pitch);
+    if (st != FDVM_OK) return st;
+    if (!b || !out_dev || !ws) return FDVM_EINVAL;
+    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    if (ws_bytes < dots_workspace_bytes(H, nscales)) return FDVM_ENOMEM;
+    return from_hip(launch_plane_dots(a, b, H, W, pitch, plane_stride, nscales, out_dev, ws,
+                                      static_cast<hipStream_t>(stream)));
 }
 
 fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,

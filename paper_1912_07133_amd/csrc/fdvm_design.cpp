@@ -16,6 +16,25 @@ namespace fdvm {
 
 namespace {
 
+// value and derivative with respect to the pole p (forward-mode derivative of
+// the closed forms below)
+struct Dual {
+    double v, d;
+};
+inline Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.d + b.d}; }
+inline Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.d - b.d}; }
+inline Dual operator-(Dual a) { return {-a.v, -a.d}; }
+inline Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+inline Dual operator/(Dual a, Dual b) { return {a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)}; }
+inline Dual operator*(double c, Dual a) { return {c * a.v, c * a.d}; }
+inline Dual operator+(double c, Dual a) { return {c + a.v, a.d}; }
+inline Dual operator-(double c, Dual a) { return {c - a.v, -a.d}; }
+inline Dual operator/(Dual a, double c) { return {a.v / c, a.d / c}; }
+inline Dual operator+(Dual a, double c) { return {a.v + c, a.d}; }
+inline Dual operator-(Dual a, double c) { return {a.v - c, a.d}; }
+inline double val(double x) { return x; }
+inline double val(Dual x) { return x.v; }
+
 // DE coefficients of the repeated-pole blur at pole p (e = 1 - p supplied
 // separately so it keeps full relative precision).
 //
@@ -31,22 +50,23 @@ namespace {
 //   b+_1  = e (1 + p) (2 + p) / 8
 //   b+_2  = -e (1 + p) (p^2 + 4p + 1) / 16
 //   a+    = [1, -2p, p^2]
-void de_coefficients(int K, double p, double e, double *b0, double bp[4], double ap[4]) {
-    for (int i = 0; i < 4; ++i) bp[i] = ap[i] = 0.0;
-    ap[0] = 1.0;
-    const double q = 1.0 + p;
+template <typename T>
+void de_coefficients_t(int K, T p, T e, T *b0, T bp[4], T ap[4]) {
+    for (int i = 0; i < 4; ++i) bp[i] = ap[i] = 0.0 * p;
+    ap[0] = 1.0 + 0.0 * p;
+    const T q = 1.0 + p;
     if (K == 3) {
         *b0 = e * (8.0 - p - p * p) / 16.0;
-        bp[1] = 3.0 * e * q * (3.0 - p * p) / 32.0;
-        bp[2] = -3.0 * p * e * q * (5.0 - p * p) / 32.0;
-        bp[3] = -e * q * (p * p * p * p - 8.0 * p * p + 1.0) / 32.0;
+        bp[1] = 3.0 * (e * q * (3.0 - p * p)) / 32.0;
+        bp[2] = -3.0 * (p * e * q * (5.0 - p * p)) / 32.0;
+        bp[3] = -(e * q * (p * p * p * p - 8.0 * (p * p) + 1.0)) / 32.0;
         ap[1] = -3.0 * p;
-        ap[2] = 3.0 * p * p;
-        ap[3] = -p * p * p;
+        ap[2] = 3.0 * (p * p);
+        ap[3] = -(p * p * p);
     } else {
         *b0 = e * (5.0 + p) / 8.0;
         bp[1] = e * q * (2.0 + p) / 8.0;
-        bp[2] = -e * q * (p * p + 4.0 * p + 1.0) / 16.0;
+        bp[2] = -(e * q * (p * p + 4.0 * p + 1.0)) / 16.0;
         ap[1] = -2.0 * p;
         ap[2] = p * p;
     }
@@ -59,17 +79,22 @@ void de_coefficients(int K, double p, double e, double *b0, double bp[4], double
 //          W_3 = -e^3 (1+p)^3 / (32 p^2)
 //   K = 2: W_1 =  e (1+p)(p^2 + 4p + 1) / (16 p)
 //          W_2 = -e^2 (1+p)^2 / (16 p)
-void cascade_weights(int K, double p, double e, double W[3]) {
-    const double q = 1.0 + p;
-    W[0] = W[1] = W[2] = 0.0;
+template <typename T>
+void cascade_weights_t(int K, T p, T e, T W[3]) {
+    const T q = 1.0 + p;
+    W[0] = W[1] = W[2] = 0.0 * p;
     if (K == 3) {
-        W[0] = -e * q * (p * p * p * p - 8.0 * p * p + 1.0) / (32.0 * p * p);
-        W[1] = e * e * q * q * (p * p + 2.0) / (32.0 * p * p);
-        W[2] = -e * e * e * q * q * q / (32.0 * p * p);
+        W[0] = -(e * q * (p * p * p * p - 8.0 * (p * p) + 1.0)) / (32.0 * (p * p));
+        W[1] = e * e * q * q * (p * p + 2.0) / (32.0 * (p * p));
+        W[2] = -(e * e * e * q * q * q) / (32.0 * (p * p));
     } else {
         W[0] = e * q * (p * p + 4.0 * p + 1.0) / (16.0 * p);
-        W[1] = -e * e * q * q / (16.0 * p);
+        W[1] = -(e * e * q * q) / (16.0 * p);
     }
+}
+
+void de_coefficients(int K, double p, double e, double *b0, double bp[4], double ap[4]) {
+    de_coefficients_t<double>(K, p, e, b0, bp, ap);
 }
 
 }  // namespace
@@ -84,16 +109,43 @@ Cascade cascade_realisation(int K, double sigma) {
     const double e = -std::expm1(-1.0 / sigma);  // 1 - p to full relative precision
     double b0, bp[4], ap[4], W[3];
     de_coefficients(K, p, e, &b0, bp, ap);
-    cascade_weights(K, p, e, W);
+    cascade_weights_t<double>(K, p, e, W);
     c.p = p;
     c.b0 = b0;
+    c.sections = K;
     double ss = 1.0;
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < MAX_SECTIONS; ++k) {
         ss /= e;
-        c.w[k] = W[k];
+        c.w[k] = k < 3 ? W[k] : 0.0;
         c.ss[k] = ss;
     }
     c.lnp = -1.0 / sigma;
+    return c;
+}
+
+// d h(n) / d sigma with p = exp(-1/sigma), dp/dsigma = p / sigma^2:
+//   h(0) = b0(p)                        -> b0'(p) dp/dsigma
+//   h(n) = sum_k W_k(p) u_k(n - 1), n >= 1, u_k(m) = C(m + k - 1, k - 1) p^m
+//   d u_k / dp = (k / p) (u_{k+1} - u_k)
+// so dh(n)/dsigma = sum_{k=1}^{K+1} w'_k u_k(n - 1) with
+//   w'_k = dp/dsigma (W_k'(p) - (k/p) W_k + ((k-1)/p) W_{k-1}),  W_0 = W_{K+1} = 0.
+Cascade sigma_derivative_realisation(int K, double sigma) {
+    Cascade c = cascade_realisation(K, sigma);
+    const double p = c.p;
+    const Dual pd{p, 1.0};
+    const Dual ed{-std::expm1(-1.0 / sigma), -1.0};
+    Dual b0, bp[4], ap[4], W[3];
+    de_coefficients_t<Dual>(K, pd, ed, &b0, bp, ap);
+    cascade_weights_t<Dual>(K, pd, ed, W);
+    const double dps = p / (sigma * sigma);
+    c.b0 = b0.d * dps;
+    for (int k = 1; k <= K + 1; ++k) {
+        const double Wk = k <= K ? W[k - 1].v : 0.0;
+        const double dWk = k <= K ? W[k - 1].d : 0.0;
+        const double Wkm = k >= 2 ? W[k - 2].v : 0.0;
+        c.w[k - 1] = dps * (dWk - (k / p) * Wk + ((k - 1) / p) * Wkm);
+    }
+    c.sections = K + 1;
     return c;
 }
 

@@ -59,8 +59,8 @@ constexpr int COL_WPB = 4;   // wavefronts (tiles) per column work-group
 
 struct ScaleArgs {
     double p, inv_p, b0, sig2;
-    double w[3];
-    double ss[3];
+    double w[MAX_SECTIONS];
+    double ss[MAX_SECTIONS];
     double pbit[7];    // p^(2^k), k = 0..6
     double pchunk[7];  // row pass: p^(C 2^k), k = 0..6
 };
@@ -136,15 +136,19 @@ __device__ __forceinline__ void cas_unstep(double inv_p, double (&v)[K], double 
     v[0] = (v[0] - x) * inv_p;
 }
 
-// v <- A^n v + z, with pn = p^n
+// v <- A^n v + z, with pn = p^n:
+//   (A^n v)_k = p^n sum_{j <= k} C(n + k - j - 1, k - j) v_j
 template <int K>
 __device__ __forceinline__ void cas_advance_add(double pn, double n, double (&v)[K], const double (&z)[K]) {
+    static_assert(K >= 2 && K <= MAX_SECTIONS, "2 to 4 sections");
+    const double c1 = n, c2 = 0.5 * n * (n + 1.0);
     const double a = v[0], b = v[1];
-    if constexpr (K == 3) {
-        const double c = v[2];
-        v[2] = fma(pn, fma(0.5 * n * (n + 1.0), a, fma(n, b, c)), z[2]);
+    if constexpr (K == 4) {
+        const double c3 = c2 * (n + 2.0) * (1.0 / 3.0);
+        v[3] = fma(pn, fma(c3, a, fma(c2, b, fma(c1, v[2], v[3]))), z[3]);
     }
-    v[1] = fma(pn, fma(n, a, b), z[1]);
+    if constexpr (K >= 3) v[2] = fma(pn, fma(c2, a, fma(c1, b, v[2])), z[2]);
+    v[1] = fma(pn, fma(c1, a, b), z[1]);
     v[0] = fma(pn, a, z[0]);
 }
 
@@ -746,7 +750,7 @@ Args make_args(const IirParams &prm, int C) {
         d.inv_p = 1.0 / q.p;
         d.b0 = q.b0;
         d.sig2 = q.sig2;
-        for (int k = 0; k < 3; ++k) {
+        for (int k = 0; k < MAX_SECTIONS; ++k) {
             d.w[k] = q.w[k];
             d.ss[k] = q.ss[k];
         }
@@ -817,6 +821,22 @@ hipError_t launch_rows_k(const void *in, int64_t H, int64_t W, int64_t in_pitch,
     return hipErrorInvalidValue;
 }
 
+// float32-plane row pass only (used for the 4-section sigma derivative)
+template <int K, typename T>
+hipError_t launch_rows_f32out(const void *in, int64_t H, int64_t W, int64_t in_pitch, void *out, int64_t out_pitch,
+                              int64_t plane_stride, const IirParams &prm, hipStream_t st) {
+#define FDVM_ROWS_CR(CC, RR) \
+    return launch_rows_t<K, CC, RR, T, false>(in, H, W, in_pitch, out, out_pitch, plane_stride, nullptr, prm, st)
+    if (W <= 64 * 8) FDVM_ROWS_CR(8, 1);
+    if (W <= 64 * 16) FDVM_ROWS_CR(16, 1);
+    if (W <= 64 * 32) FDVM_ROWS_CR(32, 1);
+    if (W <= 2 * 64 * 32) FDVM_ROWS_CR(32, 2);
+    if (W <= 4 * 64 * 32) FDVM_ROWS_CR(32, 4);
+    if (W <= 8 * 64 * 32) FDVM_ROWS_CR(32, 8);
+#undef FDVM_ROWS_CR
+    return hipErrorInvalidValue;
+}
+
 template <int K, bool FX>
 hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                           bool lap, const IirParams &prm, double *st, hipStream_t stream) {
@@ -877,6 +897,15 @@ hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int6
     }
     if (prm.order == 3) { FDVM_ROWS_DT(3) }
     if (prm.order == 2) { FDVM_ROWS_DT(2) }
+    if (prm.order == 4 && !rexp) {
+        switch (dtype) {
+            case FDVM_U16: return launch_rows_f32out<4, uint16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
+            case FDVM_F32: return launch_rows_f32out<4, float>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
+            case FDVM_F16: return launch_rows_f32out<4, _Float16>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
+            case FDVM_BF16: return launch_rows_f32out<4, bf16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
+            default: return hipErrorInvalidValue;
+        }
+    }
 #undef FDVM_ROWS_DT
     return hipErrorInvalidValue;
 }
@@ -896,6 +925,9 @@ hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_st
     if (prm.order == 2)
         return launch_cols_k<2>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, laplacian,
                                 prm, states, st);
+    if (prm.order == 4 && !rexp)
+        return launch_cols_kx<4, false>(Mid<false>{in, in_pitch, in_plane_stride, nullptr}, out, H, W, pitch,
+                                        plane_stride, laplacian, prm, states, st);
     return hipErrorInvalidValue;
 }
 

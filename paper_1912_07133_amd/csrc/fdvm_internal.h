@@ -21,14 +21,20 @@ void repeated_pole_de(int K, double p, double e, double *b0, double bp[4], doubl
 // and the mirror image for the anti-causal part.  ss[k-1] = 1/(1 - p)^k is
 // the steady-state value of v_k for a unit constant input (Eq A32 read as
 // replicate extension).
+constexpr int MAX_SECTIONS = 4;  // K = 3 blur and its sigma derivative (4 sections)
 struct Cascade {
     double p;
     double b0;
-    double w[3];
-    double ss[3];
+    double w[MAX_SECTIONS];
+    double ss[MAX_SECTIONS];
     double lnp;  // log(p), for p^n at run-time lengths
+    int sections;
 };
 Cascade cascade_realisation(int K, double sigma);
+// d h / d sigma of the same blur: b0 -> d b0 / d sigma and, since
+// d/dp of a k-fold section is (k/p)(section k+1 - section k), a cascade of
+// K + 1 sections with the same pole.
+Cascade sigma_derivative_realisation(int K, double sigma);
 
 // Coloured Savitzky-Golay / Gaussian FIR designs (float64, h(-K..K)).
 int colored_sg_taps(double sigma, int K, double omega_c, double *taps);
@@ -37,15 +43,15 @@ int gaussian_taps(double sigma, int K, double *taps);
 // ---------------------------------------------------------------- kernels
 struct IirScaleParams {
     double p, b0;
-    double w[3];
-    double ss[3];
+    double w[MAX_SECTIONS];
+    double ss[MAX_SECTIONS];
     double lnp;
     double sig2;  // sigma^2, for the fused normalised Laplacian
 };
 
 struct IirParams {
     int nscales;
-    int order;
+    int order;  // number of cascade sections (2 .. MAX_SECTIONS)
     int boundary;  // fdvm_boundary
     int pad;
     IirScaleParams s[FDVM_MAX_SCALES];
@@ -73,6 +79,18 @@ size_t detect_workspace_bytes(int64_t H, int64_t W, int nscales);
 hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                          int nscales, float tau, int border, fdvm_blob *out, int32_t cap,
                          int32_t *count, void *ws, hipStream_t stream);
+
+// Adjoint pieces (fdvm_adjoint.hip): fold of the replicate extension's
+// tails (axis 1: along y, axis 0: along x), transposed scale-normalised
+// Laplacian, per-plane float64 inner products.
+hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, float *dst, int64_t dst_pitch,
+                       int64_t dst_plane, int64_t H, int64_t W, const IirParams &prm, int axis, hipStream_t st);
+hipError_t launch_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane, int nscales,
+                                    const double *sigmas, float *out, int64_t out_pitch, int64_t out_plane,
+                                    hipStream_t st);
+size_t dots_workspace_bytes(int64_t H, int nscales);
+hipError_t launch_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch, int64_t plane,
+                             int nscales, double *out, void *ws, hipStream_t st);
 
 bool fir_mfma_available();
 // Toeplitz-block FIR on the matrix cores: y pass of `in` into tmp (nscales

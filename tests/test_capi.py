@@ -172,3 +172,43 @@ def test_batch_layout_and_validation():
     bad[1].pitch = 3
     assert ok(bad) == P.EINVAL
     assert L.fdvm_batch_detect(two, 2, filt, 2, 0, 1.0, 1, 2, ws, 16, None) == P.ENOMEM
+
+
+def test_adjoint_entry_points_validate_on_the_host():
+    L = P.lib()
+    f = P.Filter()
+    assert L.fdvm_filter_design(0, 3, 4.0, 0, ctypes.byref(f), None, 0) == P.OK
+    d = P.Filter()
+    assert L.fdvm_filter_design(3, 3, 4.0, 0, ctypes.byref(d), None, 0) == P.OK
+    assert d.kind == 3 and d.order == 3
+    filt = (P.Filter * 1)(f)
+    dfilt = (P.Filter * 1)(d)
+    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    big = 1 << 40
+    assert L.fdvm_blur_iir_adjoint(a, 8, 8, 8, 64, a, 8, 64, filt, 1, 0, ws, big, None) == P.EINVAL   # aliasing
+    assert L.fdvm_blur_iir_adjoint(a, 8, 8, 8, 64, b, 8, 64, dfilt, 1, 0, ws, big, None) == P.EINVAL  # kind
+    assert L.fdvm_blur_iir_adjoint(a, 8, 8, 8, 64, b, 8, 64, filt, 1, 0, ws, 16, None) == P.ENOMEM
+    # the sigma derivative is a per-pass filter: not accepted by the 2-D calls
+    assert L.fdvm_blur_iir(a, P.F32, 8, 8, 8, b, 8, 64, dfilt, 1, 0, ws, big, None) == P.EINVAL
+    assert L.fdvm_iir_laplacian(a, P.F32, 8, 8, 8, b, 8, 64, dfilt, 1, 0, ws, big, None) == P.EINVAL
+    assert L.fdvm_iir_pass(a, P.F32, 8, 8, 8, 64, b, 8, 64, dfilt, 1, 0, 2, ws, big, None) == P.EINVAL
+    sig = (ctypes.c_double * 1)(2.0)
+    bad = (ctypes.c_double * 1)(-1.0)
+    assert L.fdvm_laplacian_adjoint(a, 8, 8, 8, 64, 1, sig, a, 8, 64, None) == P.EINVAL
+    assert L.fdvm_laplacian_adjoint(a, 8, 8, 8, 64, 1, bad, b, 8, 64, None) == P.ERANGE
+    assert L.fdvm_plane_dots(a, b, 8, 8, 8, 64, 1, ws, ws, 1, None) == P.ENOMEM
+    assert L.fdvm_plane_dots(a, None, 8, 8, 8, 64, 1, ws, ws, big, None) == P.EINVAL
+    assert P.workspace_bytes(P.OP_BLUR_IIR_ADJOINT, 64, 64, 2) >= 2 * 64 * 64 * 4
+
+
+def test_sigma_derivative_design_matches_difference_of_designs():
+    """d b0 / d sigma of the derivative design against a central difference of
+    the blur designs (host only)."""
+    L = P.lib()
+    for order in (2, 3):
+        for s in (0.7, 2.0, 8.0, 40.0, 300.0):
+            d = P.Filter()
+            assert L.fdvm_filter_design(3, order, s, 0, ctypes.byref(d), None, 0) == P.OK
+            h = 1e-5 * s
+            num = (P.filter_design("iir", s + h, order)["b0"] - P.filter_design("iir", s - h, order)["b0"]) / (2 * h)
+            assert abs(d.b0 - num) <= 1e-6 * abs(num) + 1e-12, (order, s)
