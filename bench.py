@@ -134,6 +134,51 @@ def run_batch_leg(P, syn, torch, np, dev, stream, log):
     return out
 
 
+def run_grad_leg(P, syn, torch, np, dev, stream, log):
+    """16 float32 frames of 1024 x 1024 (the full-frame generator / 4095,
+    50 blobs each, seeds 500 + f), sigma = 3, 6, 12, 24 learnable: the fused
+    blur + normalised Laplacian forward and the hand-written backward (image and
+    sigma) of loss = sum over the detected centres of V^2, one frame after the
+    other; Mpixel*scales/s of forward + backward."""
+    cfg = syn.DIFFERENTIATION
+    sig = cfg["sigmas"]
+    frames = [torch.from_numpy(syn.normalised_frame(cfg["H"], cfg["W"], 500 + f, nblobs=cfg["nblobs"])
+                               .astype(np.float32)).to(dev) for f in range(cfg["frames"])]
+    centres = []
+    for x in frames:
+        det = P.detect_blobs(P.iir_laplacian(x, sig), 0.02, 1)
+        c = torch.tensor([(int(d["scale"]), int(d["y"]), int(d["x"])) for d in det], dtype=torch.long, device=dev)
+        centres.append(c)
+
+    def step():
+        sig_t = torch.tensor(sig, dtype=torch.float64, device=dev, requires_grad=True)
+        total = 0.0
+        for x, c in zip(frames, centres):
+            xr = x.requires_grad_(True)
+            V = P.iir_laplacian_grad(xr, sig_t)
+            loss = (V[c[:, 0], c[:, 1], c[:, 2]].double() ** 2).sum()
+            loss.backward()
+            total = total + loss.detach()
+        return sig_t.grad
+
+    step()
+    torch.cuda.synchronize()
+    reps = 3
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        g = step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    mpx = cfg["frames"] * cfg["H"] * cfg["W"] * len(sig) / 1e6
+    out = {"workload": cfg["name"], "ms_fwd_bwd": round(ms, 3), "value": round(mpx / (ms / 1e3), 1),
+           "unit": "Mpixel·scales/s (forward + backward)", "dL_dsigma": [round(float(v), 8) for v in g.cpu()],
+           "centres": int(sum(len(c) for c in centres))}
+    log(f"grad: 16 x 1024^2 x 4 scales forward + backward {ms:.2f} ms = {out['value']:.0f} Mpx*scales/s")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +187,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fir", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte scaling)")
     args = ap.parse_args()
@@ -306,6 +352,11 @@ def main() -> int:
     if not args.no_batch:
         batch = run_batch_leg(P, syn, torch, np, dev, stream, log)
 
+    # ---------------- differentiation: 16 x 1024^2, forward + backward
+    grad = None
+    if not args.no_grad:
+        grad = run_grad_leg(P, syn, torch, np, dev, stream, log)
+
     # ---------------- CPU baseline: the FP64 oracle on the same frame
     cpu = None
     parity = None
@@ -364,6 +415,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "fir": fir,
         "batch": batch,
+        "grad": grad,
         "kernels": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["GB/s"], 1), "launches": v["kernels"]}
                     for k, v in kern.items()},
         "detections": n_det,

@@ -237,6 +237,27 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
                           int nscales, fdvm_boundary bc, int algo,
                           void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * fdvm_iir_hessian -- the paper's blob detector (Section 5, Eqs 26-27) on the
+ * repeated-pole blur, fused like fdvm_iir_laplacian: per scale and pixel the
+ * Hessian H = [[D20, D11], [D11, D02]] of the blur B_s (Table I taps, d = 2
+ * central second differences, D11 the d = 1 difference along x of the d = 1
+ * difference along y, clamp-to-edge extension), formed in float64 from the
+ * unrounded blur.  `out` plane s receives sigma_s^4 |H|.  A pixel with
+ * border <= y < H - border, border <= x < W - border is a detection when
+ * sigma^4 |H| > t1 (Threshold #1) and, if t2 > 0, the Newton offset
+ * (dx, dy) = ((D01 D11 - D02 D10) / |H|, (D10 D11 - D20 D01) / |H|) has
+ * length < t2 (Threshold #2).  Detections go to out_dev in (scale, y, x)
+ * order with value sigma^4 |H| and polarity +1 where D20 < 0 (a maximum of
+ * the blur: bright blob), else -1; count_dev as fdvm_detect_blobs.
+ *   Other arguments as fdvm_iir_laplacian; ws of at least
+ *   fdvm_workspace_bytes(FDVM_OP_IIR_HESSIAN, H, W, nscales, 0) bytes.
+ */
+fdvm_status fdvm_iir_hessian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                             int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
+                             fdvm_boundary bc, float t1, float t2, int border, fdvm_blob *out_dev, int32_t cap,
+                             int32_t *count_dev, void *ws, size_t ws_bytes, void *stream);
+
 /* ------------------------------------------------------------------ adjoints
  * Transposed operators for gradients (the paper's filters are linear; these
  * are the exact transposes of the float64-defined operators).
@@ -278,7 +299,7 @@ fdvm_status fdvm_plane_dots(const float *a, const float *b, int64_t H, int64_t W
 
 /* workspace sizes */
 enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3,
-       FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5 };
+       FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5, FDVM_OP_IIR_HESSIAN = 6 };
 
 /* Bytes of device workspace `op` needs for an H x W frame with nscales
  * scales and maximum FIR half-length max_half_len (0 if unused). */

@@ -29,7 +29,7 @@ BC_REPLICATE, BC_ZERO = 0, 1
 U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
-OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS = 0, 1, 2, 3, 4, 5
+OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN = range(7)
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
 
@@ -111,6 +111,10 @@ def lib() -> ctypes.CDLL:
         L.fdvm_detect_blobs.restype = ctypes.c_int
         L.fdvm_detect_blobs.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_float,
                                         ctypes.c_int, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.fdvm_iir_hessian.restype = ctypes.c_int
+        L.fdvm_iir_hessian.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, ctypes.POINTER(Filter),
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_int, vp,
+                                       i32, vp, vp, ctypes.c_size_t, vp]
         L.fdvm_blur_iir_adjoint.restype = ctypes.c_int
         L.fdvm_blur_iir_adjoint.argtypes = [vp, i64, i64, i64, i64, vp, i64, i64, ctypes.POINTER(Filter),
                                             ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
@@ -387,6 +391,30 @@ def detect(frame, sigmas: Sequence[float], tau: float, kind: str = "iir", order:
     return detect_blobs(V, tau, border, cap), V
 
 
+def iir_hessian(x, sigmas: Sequence[float], t1: float, t2: float | None = None, border: int = 1, order: int = 3,
+                boundary: str = "replicate", cap: int = 1 << 20):
+    """The Hessian blob detector (fdvm_iir_hessian): returns (blob list,
+    sigma^4 |H| planes [S, H, W]).  t2 None disables Threshold #2."""
+    torch = _torch()
+    x = _frame(x)
+    H, W = x.shape
+    S = len(sigmas)
+    out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    filt = iir_designs(sigmas, order)
+    ws = _workspace(OP_IIR_HESSIAN, H, W, S, x.device)
+    buf = torch.empty(max(cap, 1) * BLOB_BYTES, dtype=torch.uint8, device=x.device)
+    cnt = torch.zeros(1, dtype=torch.int32, device=x.device)
+    _check(lib().fdvm_iir_hessian(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(), out.stride(1),
+                                  out.stride(0), filt, S, BOUNDARIES[boundary], float(t1),
+                                  float(t2) if t2 is not None else 0.0, int(border), buf.data_ptr(), int(cap),
+                                  cnt.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(x.device)),
+           "fdvm_iir_hessian")
+    n = int(cnt.item())
+    if n > cap:
+        raise FdvmError(EOVERFLOW, f"fdvm_iir_hessian: {n} detections > cap {cap}")
+    return buf[: n * BLOB_BYTES].cpu().numpy().view(BLOB_DTYPE).copy(), out
+
+
 # ------------------------------------------------------------------ gradients
 def _planes(t):
     torch = _torch()
@@ -604,5 +632,5 @@ def scale_of(sigma: float) -> float:
 __all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "iir_laplacian", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
            "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of",
            "Batch", "autotune_batch", "row_chunk_choices", "Frame", "blur_iir_adjoint", "laplacian_adjoint",
-           "plane_dots", "dblur_dsigma_parts", "iir_laplacian_grad"]
+           "plane_dots", "dblur_dsigma_parts", "iir_laplacian_grad", "iir_hessian"]
 _ = math

@@ -122,6 +122,10 @@ size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_h
             return (((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255) +
                    iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS);
         case FDVM_OP_PLANE_DOTS: return dots_workspace_bytes(H, nscales);
+        case FDVM_OP_IIR_HESSIAN:
+            return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
+                   iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H) +
+                   2 * detect_workspace_bytes(H, W, nscales);
         default: return 0;
     }
 }
@@ -249,6 +253,47 @@ fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
     if (e != hipSuccess) return FDVM_EDEVICE;
     return from_hip(
         launch_iir_cols(rows, W, rstride, rexp, out, H, W, out_pitch, plane_stride, true, prm, states, hs));
+}
+
+fdvm_status fdvm_iir_hessian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                             int64_t out_pitch, int64_t plane_stride, const fdvm_filter *filters, int nscales,
+                             fdvm_boundary bc, float t1, float t2, int border, fdvm_blob *out_dev, int32_t cap,
+                             int32_t *count_dev, void *ws, size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
+    if (!out_dev || !count_dev || cap < 0 || border < 0 || !std::isfinite(t1) || !std::isfinite(t2))
+        return FDVM_EINVAL;
+    IirParams prm;
+    st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
+    if (!ws) return FDVM_EINVAL;
+    const size_t plane_bytes = ((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255;
+    const size_t st_bytes = iir_cols_workspace_bytes(H, W, nscales, prm.order);
+    const size_t rx_bytes = iir_rexp_bytes(H);
+    const size_t det_bytes = detect_workspace_bytes(H, W, nscales);
+    if (ws_bytes < plane_bytes * nscales + st_bytes + rx_bytes + 2 * det_bytes) return FDVM_ENOMEM;
+    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    // ws: x-pass fixed-point planes | column states | row exponents |
+    //     detection words + counts | bright-polarity words
+    char *w = static_cast<char *>(ws);
+    int32_t *rows = reinterpret_cast<int32_t *>(w);
+    const int64_t rstride = (int64_t)(plane_bytes / sizeof(int32_t));
+    void *states = w + plane_bytes * nscales;
+    int *rexp = reinterpret_cast<int *>(w + plane_bytes * nscales + st_bytes);
+    void *det = w + plane_bytes * nscales + st_bytes + rx_bytes;
+    unsigned long long *pmask = reinterpret_cast<unsigned long long *>(static_cast<char *>(det) + det_bytes);
+    HessArgs hz{t1, t2, border, 0, detect_mask_words(det), pmask};
+    hipError_t e = launch_iir_rows(in, dt, H, W, in_pitch, rows, W, rstride, rexp, 0, prm, hs);
+    if (e == hipSuccess)
+        e = launch_iir_cols_mode(rows, W, rstride, rexp, out, H, W, out_pitch, plane_stride, COLS_HESSIAN, &hz, prm,
+                                 states, hs);
+    if (e == hipSuccess)
+        e = launch_compact(out, H, W, out_pitch, plane_stride, nscales, pmask, out_dev, cap, count_dev, det, hs);
+    return from_hip(e);
 }
 
 fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,

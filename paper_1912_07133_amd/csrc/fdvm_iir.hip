@@ -573,11 +573,13 @@ __device__ __forceinline__ void wait_lds_dma() { asm volatile("s_waitcnt vmcnt(0
 // then every quarter, top first, is swept backwards from its recorded state
 // and finished by the forward sweep, which runs through the whole tile.
 constexpr int FIN_WPB = 4;  // wavefronts (tiles) per final-pass work-group
+constexpr int FIN_BLUR = 0, FIN_LAPLACIAN = 1, FIN_HESSIAN = 2;
 
-template <int K, bool LAP, bool FX>
+template <int K, int MODE, bool FX>
 __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
     Mid<FX> m, float *out, int64_t out_pitch, int64_t out_plane_stride, int H, int W, int nty, int ntx,
-    const double *__restrict__ st, Args a) {
+    const double *__restrict__ st, Args a, HessArgs hz) {
+    constexpr bool LAP = MODE != FIN_BLUR;   // second differences need the neighbour rows and columns
     constexpr int QT = 16;
     constexpr int NQ = CT / QT;
     constexpr int NR = LAP ? CT + 2 : CT;   // staged rows: (y0 - 1 if LAP) .. y0 + CT - 1 (.. y0 + CT if LAP)
@@ -651,8 +653,37 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
         auto emit = [&](int y, double bmv, double bcv, double bnv) {
             const double bl = lane_left_d(bcv);
             const double br = lane_right_d(bcv);
-            const double v = sig2 * fma(-4.0, bcv, (bl + br) + (bmv + bnv));
-            if (wr) dst[(int64_t)y * out_pitch + col] = (float)v;
+            if constexpr (MODE == FIN_LAPLACIAN) {
+                const double v = sig2 * fma(-4.0, bcv, (bl + br) + (bmv + bnv));
+                if (wr) dst[(int64_t)y * out_pitch + col] = (float)v;
+            } else if constexpr (MODE == FIN_HESSIAN) {
+                // Table I taps: d = 2 central second differences, d = 1 half
+                // central differences, D11 = D10 of D01 (Eqs 26-27)
+                const double d20 = (bl + br) - 2.0 * bcv;
+                const double d02 = (bmv + bnv) - 2.0 * bcv;
+                const double d10 = 0.5 * (br - bl);
+                const double d01 = 0.5 * (bnv - bmv);
+                const double d11 = 0.25 * ((lane_right_d(bnv) - lane_left_d(bnv)) - (lane_right_d(bmv) - lane_left_d(bmv)));
+                const double det = fma(d20, d02, -d11 * d11);
+                const double ndet = sig2 * sig2 * det;
+                bool hit = ndet > (double)hz.t1;
+                if (hz.t2 > 0.0f) {
+                    const double dx = (d01 * d11 - d02 * d10) / det;
+                    const double dy = (d10 * d11 - d20 * d01) / det;
+                    hit = hit && dx * dx + dy * dy < (double)hz.t2 * (double)hz.t2;
+                }
+                const bool inside = wr && col >= hz.border && col < W - hz.border && y >= hz.border &&
+                                    y < H - hz.border;
+                hit = hit && inside;
+                const unsigned long long bits = __ballot(hit) >> 1;            // lanes 1..62 -> bits 0..61
+                const unsigned long long bright = __ballot(hit && d20 < 0.0) >> 1;
+                if (wr) dst[(int64_t)y * out_pitch + col] = (float)ndet;
+                if (lane == 0) {
+                    const int64_t wi = ((int64_t)s * H + y) * ntx + tx;
+                    hz.mask[wi] = bits;
+                    hz.pmask[wi] = bright;
+                }
+            }
         };
         // states entering each quarter from below
 #pragma unroll
@@ -839,7 +870,7 @@ hipError_t launch_rows_f32out(const void *in, int64_t H, int64_t W, int64_t in_p
 
 template <int K, bool FX>
 hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
-                          bool lap, const IirParams &prm, double *st, hipStream_t stream) {
+                          int mode, const HessArgs *hp, const IirParams &prm, double *st, hipStream_t stream) {
     Args a = make_args(prm, 1);
     const int nty = (int)((H + CT - 1) / CT);
     const unsigned S = (unsigned)prm.nscales;
@@ -853,29 +884,34 @@ hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t p
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int ntyg = (nty + FIN_WPB - 1) / FIN_WPB;
-    if (lap) {
+    const HessArgs hz = hp ? *hp : HessArgs{};
+    if (mode != FIN_BLUR) {
         const int ntx = (int)((W + 61) / 62);
         const unsigned nb = (unsigned)ntx * (unsigned)ntyg * S;
-        hipLaunchKernelGGL((iir_col_final_kernel<K, true, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream, m, out,
-                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a);
+        if (mode == FIN_HESSIAN)
+            hipLaunchKernelGGL((iir_col_final_kernel<K, FIN_HESSIAN, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream,
+                               m, out, pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a, hz);
+        else
+            hipLaunchKernelGGL((iir_col_final_kernel<K, FIN_LAPLACIAN, FX>), dim3(nb), dim3(FIN_WPB * 64), 0,
+                               stream, m, out, pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a, hz);
     } else {
         const int ntx = (int)((W + 63) / 64);
         const unsigned nb = (unsigned)ntx * (unsigned)ntyg * S;
-        hipLaunchKernelGGL((iir_col_final_kernel<K, false, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream, m, out,
-                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a);
+        hipLaunchKernelGGL((iir_col_final_kernel<K, FIN_BLUR, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream, m, out,
+                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a, hz);
     }
     return hipGetLastError();
 }
 
 template <int K>
 hipError_t launch_cols_k(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp, float *out,
-                         int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool lap,
+                         int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, int mode, const HessArgs *hp,
                          const IirParams &prm, double *st, hipStream_t stream) {
     if (rexp)
         return launch_cols_kx<K, true>(Mid<true>{in, in_pitch, in_plane_stride, rexp}, out, H, W, pitch,
-                                       plane_stride, lap, prm, st, stream);
+                                       plane_stride, mode, hp, prm, st, stream);
     return launch_cols_kx<K, false>(Mid<false>{in, in_pitch, in_plane_stride, nullptr}, out, H, W, pitch,
-                                    plane_stride, lap, prm, st, stream);
+                                    plane_stride, mode, hp, prm, st, stream);
 }
 
 }  // namespace
@@ -918,16 +954,24 @@ size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order) {
 hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp, float *out,
                            int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, bool laplacian,
                            const IirParams &prm, void *ws, hipStream_t st) {
+    return launch_iir_cols_mode(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride,
+                                laplacian ? FIN_LAPLACIAN : FIN_BLUR, nullptr, prm, ws, st);
+}
+
+hipError_t launch_iir_cols_mode(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp,
+                                float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, int mode,
+                                const HessArgs *hp, const IirParams &prm, void *ws, hipStream_t st) {
     double *states = static_cast<double *>(ws);
+    if (mode == FIN_HESSIAN && !hp) return hipErrorInvalidValue;
     if (prm.order == 3)
-        return launch_cols_k<3>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, laplacian,
-                                prm, states, st);
+        return launch_cols_k<3>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, mode, hp, prm,
+                                states, st);
     if (prm.order == 2)
-        return launch_cols_k<2>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, laplacian,
-                                prm, states, st);
-    if (prm.order == 4 && !rexp)
+        return launch_cols_k<2>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, mode, hp, prm,
+                                states, st);
+    if (prm.order == 4 && !rexp && mode != FIN_HESSIAN)
         return launch_cols_kx<4, false>(Mid<false>{in, in_pitch, in_plane_stride, nullptr}, out, H, W, pitch,
-                                        plane_stride, laplacian, prm, states, st);
+                                        plane_stride, mode, hp, prm, states, st);
     return hipErrorInvalidValue;
 }
 

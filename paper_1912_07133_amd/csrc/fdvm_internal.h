@@ -70,12 +70,32 @@ inline size_t iir_rexp_bytes(int64_t H) { return ((size_t)H * sizeof(int) + 255)
 hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp,
                            float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                            bool laplacian, const IirParams &prm, void *ws, hipStream_t stream);
+// The column pass finished as the Hessian detector (Section 5, Eqs 26-27):
+// out receives sigma^4 |H| per pixel; mask / pmask (one word per (scale, row,
+// 62-column tile), the detection words' layout) receive the pixels passing
+// Threshold #1 (and #2 when t2 > 0) and, of those, the bright ones (D20 < 0).
+struct HessArgs {
+    float t1, t2;
+    int border, pad;
+    unsigned long long *mask, *pmask;
+};
+hipError_t launch_iir_cols_mode(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp,
+                                float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, int mode,
+                                const HessArgs *hp, const IirParams &prm, void *ws, hipStream_t stream);
+constexpr int COLS_HESSIAN = 2;   // launch_iir_cols_mode: 0 blur, 1 Laplacian, 2 Hessian
 
 hipError_t launch_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                            int nscales, const float *norms, unsigned what,
                            float *out, int64_t out_plane_stride, hipStream_t stream);
 
 size_t detect_workspace_bytes(int64_t H, int64_t W, int nscales);
+// the detection words (mask) of a workspace laid out by detect_workspace_bytes
+unsigned long long *detect_mask_words(void *ws);
+// compaction of given detection words into the ordered list; values read from
+// resp, polarity from pmask (null: the sign of the value)
+hipError_t launch_compact(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                          int nscales, const unsigned long long *pmask, fdvm_blob *out, int32_t cap,
+                          int32_t *count, void *ws, hipStream_t stream);
 hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                          int nscales, float tau, int border, fdvm_blob *out, int32_t cap,
                          int32_t *count, void *ws, hipStream_t stream);

@@ -309,6 +309,7 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_counts_kernel(const int *__re
 __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *__restrict__ V, int64_t pitch,
                                                                    int64_t plane_stride, int H, int W, int ntx,
                                                                    const unsigned long long *__restrict__ mask,
+                                                                   const unsigned long long *__restrict__ pmask,
                                                                    int64_t nwords, const int *__restrict__ boff,
                                                                    fdvm_blob *__restrict__ out, int cap) {
     constexpr int NW = SUM_THREADS * SUM_WORDS;
@@ -345,6 +346,7 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
         const int tx = (int)(word - sy * (unsigned)ntx);
         const int s = (int)(sy / (unsigned)H);
         const int y = (int)(sy - (unsigned)s * (unsigned)H);
+        const unsigned long long pbits = pmask ? pmask[bbase + first + i] : 0ull;
         while (bits) {
             const int b = __ffsll((long long)bits) - 1;
             bits &= bits - 1;
@@ -355,7 +357,7 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
                 rec.y = y;
                 rec.x = xx;
                 rec.scale = s;
-                rec.polarity = v < 0.0f ? 1 : -1;
+                rec.polarity = pmask ? (((pbits >> b) & 1ull) ? 1 : -1) : (v < 0.0f ? 1 : -1);
                 rec.value = v;
                 out[idx] = rec;
             }
@@ -405,28 +407,38 @@ size_t detect_workspace_bytes(int64_t H, int64_t W, int nscales) {
     return d.mask_bytes + d.sums_bytes;
 }
 
-hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
-                         int nscales, float tau, int border, fdvm_blob *out, int32_t cap, int32_t *count,
-                         void *ws, hipStream_t st) {
+unsigned long long *detect_mask_words(void *ws) { return static_cast<unsigned long long *>(ws); }
+
+hipError_t launch_compact(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                          int nscales, const unsigned long long *pmask, fdvm_blob *out, int32_t cap,
+                          int32_t *count, void *ws, hipStream_t st) {
     const DetectLayout d = detect_layout(H, W, nscales);
     unsigned long long *mask = static_cast<unsigned long long *>(ws);
     int *bsum = reinterpret_cast<int *>(static_cast<char *>(ws) + d.mask_bytes);
     int *boff = bsum + d.nblocks;
-    dim3 g1((unsigned)d.ntx, (unsigned)((H + DT_ROWS * DT_WAVES - 1) / (DT_ROWS * DT_WAVES)));
-    hipLaunchKernelGGL(detect_mask_kernel, g1, dim3(DT_WAVES * 64), 0, st, resp, pitch, plane_stride, nscales,
-                       (int)H, (int)W, tau, border, mask, d.ntx);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(detect_sums_kernel, dim3((unsigned)d.nblocks), dim3(SUM_THREADS), 0, st, mask, d.nwords,
                        bsum);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, bsum, (int)d.nblocks, boff, count);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(detect_emit_kernel, dim3((unsigned)d.nblocks), dim3(SUM_THREADS), 0, st, resp, pitch,
-                       plane_stride, (int)H, (int)W, d.ntx, mask, d.nwords, boff, out, cap);
+                       plane_stride, (int)H, (int)W, d.ntx, mask, pmask, d.nwords, boff, out, cap);
     return hipGetLastError();
+}
+
+hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                         int nscales, float tau, int border, fdvm_blob *out, int32_t cap, int32_t *count,
+                         void *ws, hipStream_t st) {
+    const DetectLayout d = detect_layout(H, W, nscales);
+    unsigned long long *mask = static_cast<unsigned long long *>(ws);
+    dim3 g1((unsigned)d.ntx, (unsigned)((H + DT_ROWS * DT_WAVES - 1) / (DT_ROWS * DT_WAVES)));
+    hipLaunchKernelGGL(detect_mask_kernel, g1, dim3(DT_WAVES * 64), 0, st, resp, pitch, plane_stride, nscales,
+                       (int)H, (int)W, tau, border, mask, d.ntx);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_compact(resp, H, W, pitch, plane_stride, nscales, nullptr, out, cap, count, ws, st);
 }
 
 }  // namespace fdvm

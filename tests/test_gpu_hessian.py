@@ -1,0 +1,81 @@
+"""GPU parity of fdvm_iir_hessian (Section 5, Eqs 26-27) against the FP64
+oracle's detect_hessian on the oracle blur.
+
+sigma^4 |H| is compared plane by plane; the detected pixel sets must agree
+except where a decision is within rounding of a threshold: |ndet - T1| within
+twice the measured plane error, or a Newton offset within 1e-4 (relative) of
+T2.  Polarity (bright where D20 < 0) is compared on the common detections."""
+
+import numpy as np
+import pytest
+
+import synthetic as syn
+from oracle import design, filtering, shape
+from parity import say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_1912_07133_amd")
+
+
+def check(frame_dev, x64, sigmas, t1_frac, t2, border=1, order=3):
+    B = filtering.blur_bank(x64, [design.repeated_pole(order, s) for s in sigmas])
+    refs = [shape.detect_hessian(B[s], sg, 0.0, None, border) for s, sg in enumerate(sigmas)]
+    t1 = t1_frac * max(float(np.max(r[1])) for r in refs)
+    det, nd = P.iir_hessian(frame_dev, sigmas, t1, t2, border, order=order)
+    nd = nd.cpu().numpy().astype(np.float64)
+    got = {(int(d["scale"]), int(d["y"]), int(d["x"])): int(d["polarity"]) for d in det}
+    nfrag = 0
+    nref = 0
+    for s, sg in enumerate(sigmas):
+        mask, ndet, dx, dy = shape.detect_hessian(B[s], sg, t1, t2, border)
+        err = float(np.max(np.abs(nd[s] - ndet)))
+        scale = float(np.max(np.abs(ndet)))
+        assert err <= 1e-4 * scale + 1e-6, (s, err, scale)
+        frag = np.abs(ndet - t1) <= 2 * err + 1e-12
+        if t2 is not None:
+            off = np.sqrt(dx * dx + dy * dy)
+            frag |= np.abs(off - t2) <= 1e-4 * t2
+        nfrag += int(np.sum(frag & mask))
+        nref += int(np.sum(mask))
+        H, W = mask.shape
+        gmask = np.zeros_like(mask)
+        for (ss, y, x) in got:
+            if ss == s:
+                gmask[y, x] = True
+        diff = (gmask != mask) & ~frag
+        assert not diff.any(), (s, np.argwhere(diff)[:5])
+        d20 = shape.derivative(B[s], 2, 0)
+        for (ss, y, x), pol in got.items():
+            if ss == s and mask[y, x] and abs(d20[y, x]) > 1e-9 * scale:
+                assert pol == (1 if d20[y, x] < 0 else -1), (s, y, x)
+    say(f"   detections gpu={len(got)} ref={nref} fragile={nfrag}")
+    return len(got)
+
+
+def test_tiny_frame_threshold_1_and_2():
+    say("case: hessian tiny 256x256 sigma=4")
+    img = syn.tiny_frame(0)
+    x = torch.from_numpy(img.astype(np.float32)).cuda()
+    n = check(x, img.astype(np.float32).astype(np.float64), [4.0], 0.05, None)
+    assert n > 0
+    check(x, img.astype(np.float32).astype(np.float64), [4.0], 0.05, 1.0)
+
+
+@pytest.mark.parametrize("shape_", [(1, 1), (5, 70), (63, 62), (64, 125), (200, 333)])
+def test_ragged_multi_scale(shape_):
+    H, W = shape_
+    say(f"case: hessian ragged {H}x{W}")
+    a = syn.aerial_frame(H, W, 7 + H, nblobs=max(2, H * W // 10000)).astype(np.float64)
+    x = torch.from_numpy(a.astype(np.float32)).cuda()
+    check(x, a, [1.5, 4.0, 9.0], 0.02, 0.8, border=0 if H < 3 else 1)
+
+
+def test_full_frame_sigma_ladder():
+    cfg = syn.FULL_FRAME
+    say("case: hessian full frame 2048x2048 u16 8 scales")
+    frame = syn.aerial_frame(cfg["H"], cfg["W"], cfg["seed"])
+    x = torch.from_numpy(frame.view(np.int16)).cuda()
+    n = check(x, frame.astype(np.float64), cfg["sigmas"], 0.002, 1.0)
+    assert n > 50
