@@ -179,6 +179,71 @@ def run_grad_leg(P, syn, torch, np, dev, stream, log):
     return out
 
 
+def run_precision_leg(P, syn, torch, np, dev, stream, log):
+    """One 8192 x 8192 frame (generator seed 3, 3200 blobs, / 4095) stored as
+    float16 and as bfloat16; coloured SG FIR of lengths 33, 65, 129, 257
+    (sigma = K / 3, direct and Toeplitz/MFMA) and the K = 3 IIR at the same
+    sigmas.  Throughput per form, and per scale the largest relative error
+    against float64 direct 2-D sums on 16 sampled pixels, for the stored and
+    for the original input (the IIR's impulse response truncated at 30 sigma)."""
+    from oracle import design, filtering   # error reference only
+
+    cfg = syn.PRECISION
+    Ks = [(m - 1) // 2 for m in cfg["fir_lengths"]]
+    sig = [k / 3 for k in Ks]
+    orig = syn.normalised_frame(cfg["H"], cfg["W"], cfg["seed"], nblobs=cfg["nblobs"])
+    rng = np.random.default_rng(5)
+    pts = [tuple(p) for p in rng.integers(0, cfg["H"], (16, 2))]
+    mpx = cfg["H"] * cfg["W"] * len(sig) / 1e6
+
+    def sampled(img, h):
+        K = (len(h) - 1) // 2
+        r = np.arange(-K, K + 1)
+        H, W = img.shape
+        return np.array([h @ img[np.ix_(np.clip(i - r, 0, H - 1), np.clip(j - r, 0, W - 1))] @ h for i, j in pts])
+
+    taps = {"fir": [design.colored_sg_taps(s, K=K) for s, K in zip(sig, Ks)]}
+    iir_h = []
+    for s in sig:
+        half = int(30 * s) + 8
+        iir_h.append(filtering.impulse_response_by_recursion(design.repeated_pole(3, s), half))
+    taps["iir"] = iir_h
+    out = {"workload": cfg["name"], "scales": [round(s, 4) for s in sig], "fir_lengths": cfg["fir_lengths"],
+           "error": "max |gpu - fp64| / max |fp64| over 16 sampled pixels, per scale", "forms": {}}
+    for kind, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        xt = torch.from_numpy(orig.astype(np.float32)).to(tdt)
+        deq = xt.float().numpy().astype(np.float64)
+        x = xt.to(dev)
+        runs = {"iir": lambda: P.blur_iir(x, sig, order=3),
+                "fir_direct": lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=P.FIR_DIRECT),
+                "fir_mfma": lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=P.FIR_TOEPLITZ_MFMA)}
+        for name, fn in runs.items():
+            B = fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(3):
+                B = fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / 3
+            Bn = B.cpu().numpy()
+            hs = taps["iir" if name == "iir" else "fir"]
+            eq, eo = [], []
+            for s in range(len(sig)):
+                g = np.array([Bn[s, i, j] for i, j in pts], dtype=np.float64)
+                rq, ro = sampled(deq, hs[s]), sampled(orig, hs[s])
+                eq.append(float(np.max(np.abs(g - rq)) / np.max(np.abs(rq))))
+                eo.append(float(np.max(np.abs(g - ro)) / np.max(np.abs(ro))))
+            out["forms"][f"{kind}_{name}"] = {"ms": round(ms, 3), "value": round(mpx / (ms / 1e3), 1),
+                                             "err_vs_stored": [float(f"{v:.3g}") for v in eq],
+                                             "err_vs_original": [float(f"{v:.3g}") for v in eo]}
+            del B
+        log(f"precision {kind}: " + ", ".join(f"{k.split('_', 1)[1]} {v['ms']:.2f} ms max err {max(v['err_vs_original']):.2e}"
+                                            for k, v in out["forms"].items() if k.startswith(kind)))
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +253,7 @@ def main() -> int:
     ap.add_argument("--no-fir", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte scaling)")
     args = ap.parse_args()
@@ -357,6 +423,11 @@ def main() -> int:
     if not args.no_grad:
         grad = run_grad_leg(P, syn, torch, np, dev, stream, log)
 
+    # ---------------- reduced-precision storage: 8192^2 float16 / bfloat16
+    precision = None
+    if not args.no_precision:
+        precision = run_precision_leg(P, syn, torch, np, dev, stream, log)
+
     # ---------------- CPU baseline: the FP64 oracle on the same frame
     cpu = None
     parity = None
@@ -416,6 +487,7 @@ def main() -> int:
         "fir": fir,
         "batch": batch,
         "grad": grad,
+        "precision": precision,
         "kernels": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["GB/s"], 1), "launches": v["kernels"]}
                     for k, v in kern.items()},
         "detections": n_det,
