@@ -128,17 +128,33 @@ __device__ __forceinline__ int key_right(int k) { return __builtin_amdgcn_mov_dp
 // The planes reach LDS by direct global-to-LDS copies issued DT_NPL - 1
 // planes ahead of use; the mask words of the wavefront collect in LDS and are
 // written once at the end (no stores interleave with the counted copies).
-// Per plane and output row the kernel keeps the 3 x 3 minimum / maximum key
-// (centre included) and the 8-neighbour ones (centre excluded); the planes
-// rotate through three register roles (previous, current, next), so the
-// scale loop is unrolled by three.
+// Per plane and output row the kernel keeps two 3 x 3 statistics (centre
+// included) and the same without the centre; the planes rotate through three
+// register roles (previous, current, next), so the scale loop is unrolled by
+// three.  A missing plane (before the first, after the last) is a plane of
+// sentinels.
+//
+// RAW (tau > 0): a bright candidate is negative and a dark one positive, and
+// for such a centre the float order against any neighbour is an integer order
+// of the raw bit patterns: for c < 0, c < n exactly when bits(c) > bits(n) as
+// unsigned integers (negative floats above every non-negative one, larger
+// magnitude higher); for c > 0, c > n exactly when bits(c) > bits(n) as signed
+// integers.  The statistics are then the unsigned and the signed maximum of
+// the raw bits (sentinels 0 and INT32_MIN), and no key transform is needed.
+// Otherwise (tau = 0, where a zero centre may be an extremum) they are the
+// minimum and maximum of order-preserving keys (fkey; sentinels INT32_MAX and
+// INT32_MIN).
+template <bool RAW>
 __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float *__restrict__ V, int64_t pitch,
                                                                      int64_t plane_stride, int S, int H, int W,
                                                                      float tau, int border,
                                                                      unsigned long long *__restrict__ mask,
                                                                      int ntx) {
     constexpr int RB = DT_ROWS;
-    constexpr int KMAX = 0x7fffffff, KMIN = (int)0x80000000;
+    constexpr int IMAX = 0x7fffffff, IMIN = (int)0x80000000;
+    // sentinels of the two statistics: lo (bright test) and hi (dark test)
+    constexpr int LO_NONE = RAW ? 0 : IMAX;
+    constexpr int HI_NONE = IMIN;
     __shared__ uint32_t ring[DT_WAVES][DT_NPL][(RB + 2) * 64];
     __shared__ unsigned long long words[DT_WAVES][FDVM_MAX_SCALES * RB];
     const int lane = threadIdx.x & 63;
@@ -162,10 +178,21 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     };
     constexpr int AHEAD = (DT_NPL - 1) * (RB + 2);  // copies issued after the plane awaited
     struct Plane {
-        int c[RB];               // centre keys of the output rows
-        int m9[RB], M9[RB];      // 3 x 3 minimum / maximum
-        int m8[RB], M8[RB];      // the same without the centre
+        int c[RB];               // centre (raw bits or key) of the output rows
+        int lo9[RB], hi9[RB];    // 3 x 3 statistics
+        int lo8[RB], hi8[RB];    // the same without the centre
     };
+    // the two statistics of a pair / triple of values
+    auto lo2 = [](int a, int b) {
+        if constexpr (RAW) return (int)max((unsigned)a, (unsigned)b);
+        else return min(a, b);
+    };
+    auto lo3 = [](int a, int b, int c) {
+        if constexpr (RAW) return (int)max(max((unsigned)a, (unsigned)b), (unsigned)c);
+        else return min(min(a, b), c);
+    };
+    auto hi2 = [](int a, int b) { return max(a, b); };
+    auto hi3 = [](int a, int b, int c) { return max(max(a, b), c); };
     // statistics of plane s (its copies must have landed).  EDGE: the band
     // touches the image border (some rows or lanes outside get sentinels);
     // otherwise every staged sample is inside and no test is needed.
@@ -173,53 +200,66 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         constexpr bool EDGE = decltype(edge_tag)::value;
         uint32_t raw[RB + 2];
         read10(rg + (s % DT_NPL) * (RB + 2) * 64 + lane, raw);
-        int rmin[RB + 2], rmax[RB + 2], lrmin[RB + 2], lrmax[RB + 2];
+        int rlo[RB + 2], rhi[RB + 2], llo[RB + 2], lhi[RB + 2];
 #pragma unroll
         for (int r = 0; r < RB + 2; ++r) {
-            const int k = fkey(__uint_as_float(raw[r]));
+            const int k = RAW ? (int)raw[r] : fkey(__uint_as_float(raw[r]));
             if constexpr (EDGE) {
                 const int y = y0 - 1 + r;
                 const bool yin = y >= 0 && y < H;   // wave-uniform
-                const int kmin = xin ? k : KMAX, kmax = xin ? k : KMIN;
-                const int lmin = min(key_left(kmin), key_right(kmin));
-                const int lmax = max(key_left(kmax), key_right(kmax));
-                lrmin[r] = yin ? lmin : KMAX;
-                lrmax[r] = yin ? lmax : KMIN;
-                rmin[r] = yin ? min(lmin, kmin) : KMAX;
-                rmax[r] = yin ? max(lmax, kmax) : KMIN;
+                const int klo = xin ? k : LO_NONE, khi = xin ? k : HI_NONE;
+                const int l = lo2(key_left(klo), key_right(klo));
+                const int h = hi2(key_left(khi), key_right(khi));
+                llo[r] = yin ? l : LO_NONE;
+                lhi[r] = yin ? h : HI_NONE;
+                rlo[r] = yin ? lo2(l, klo) : LO_NONE;
+                rhi[r] = yin ? hi2(h, khi) : HI_NONE;
             } else {
                 const int kl = key_left(k), kr = key_right(k);
-                lrmin[r] = min(kl, kr);
-                lrmax[r] = max(kl, kr);
-                rmin[r] = min(min(kl, kr), k);
-                rmax[r] = max(max(kl, kr), k);
+                llo[r] = lo2(kl, kr);
+                lhi[r] = hi2(kl, kr);
+                rlo[r] = lo3(kl, kr, k);
+                rhi[r] = hi3(kl, kr, k);
             }
             if (r >= 1 && r <= RB) pl.c[r - 1] = k;
         }
-        // three-operand minima / maxima with single-use inner terms (v_min3 / v_max3)
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
-            pl.m8[r] = min(min(rmin[r], lrmin[r + 1]), rmin[r + 2]);
-            pl.M8[r] = max(max(rmax[r], lrmax[r + 1]), rmax[r + 2]);
-            pl.m9[r] = min(min(rmin[r], rmin[r + 1]), rmin[r + 2]);
-            pl.M9[r] = max(max(rmax[r], rmax[r + 1]), rmax[r + 2]);
+            pl.lo8[r] = lo3(rlo[r], llo[r + 1], rlo[r + 2]);
+            pl.hi8[r] = hi3(rhi[r], lhi[r + 1], rhi[r + 2]);
+            pl.lo9[r] = lo3(rlo[r], rlo[r + 1], rlo[r + 2]);
+            pl.hi9[r] = hi3(rhi[r], rhi[r + 1], rhi[r + 2]);
+        }
+    };
+    auto absent = [&](Plane &pl) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            pl.lo9[r] = LO_NONE;
+            pl.hi9[r] = HI_NONE;
         }
     };
     const int kneg = fkey(-tau), kpos = fkey(tau);
     const bool xout = lane >= 1 && lane <= 62 && x < W && x >= border && x < W - border;
     unsigned long long *wd = words[wv];
-    // decisions at plane s from its neighbours in scale (absent ones skipped)
-    auto decide = [&](int s, const Plane &pv, const Plane &pc, const Plane &pn, bool hp, bool hn) {
+    // decisions at plane s from its neighbours in scale
+    auto decide = [&](int s, const Plane &pv, const Plane &pc, const Plane &pn) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             const int y = y0 + r;
-            const int lo = min(min(pc.m8[r], hp ? pv.m9[r] : KMAX), hn ? pn.m9[r] : KMAX);
-            const int hi = max(max(pc.M8[r], hp ? pv.M9[r] : KMIN), hn ? pn.M9[r] : KMIN);
+            const int lo = lo3(pc.lo8[r], pv.lo9[r], pn.lo9[r]);
+            const int hi = hi3(pc.hi8[r], pv.hi9[r], pn.hi9[r]);
             const int k = pc.c[r];
             const bool inside = xout && y < H && y >= border && y < H - border;
             // no neighbour at all (1 x 1 x 1 stack) compares as "strict" too
-            const bool bright = inside && k <= kneg && k < lo;
-            const bool dark = inside && k >= kpos && k > hi;
+            bool bright, dark;
+            if constexpr (RAW) {
+                const float v = __int_as_float(k);
+                bright = inside && v <= -tau && (unsigned)k > (unsigned)lo;
+                dark = inside && v >= tau && k > hi;
+            } else {
+                bright = inside && k <= kneg && k < lo;
+                dark = inside && k >= kpos && k > hi;
+            }
             const unsigned long long bits = __ballot(bright || dark) >> 1;  // lanes 1..62 -> bits 0..61
             if (lane == 0) wd[s * RB + r] = bits;
         }
@@ -228,6 +268,7 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     for (int q = 0; q < DT_NPL; ++q) request(q);
     auto run = [&](auto edge_tag) {
         Plane P0, P1, P2;
+        absent(P2);         // the plane before the first
         wait_vm<AHEAD>();   // plane 0
         stats(0, P0, edge_tag);
         // step at plane s: plane s + 1 is needed now; plane s's slot is free
@@ -235,9 +276,11 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         auto step = [&](int s, Plane &pv, Plane &pc, Plane &pn) {
             request(s + DT_NPL);
             wait_vm<AHEAD>();
-            const bool hn = s + 1 < S;
-            if (hn) stats(s + 1, pn, edge_tag);
-            decide(s, pv, pc, pn, s > 0, hn);
+            if (s + 1 < S)
+                stats(s + 1, pn, edge_tag);
+            else
+                absent(pn);
+            decide(s, pv, pc, pn);
         };
         for (int s = 0; s < S; s += 3) {
             step(s, P2, P0, P1);
@@ -306,6 +349,31 @@ __global__ __launch_bounds__(SCAN_BLOCK) void scan_counts_kernel(const int *__re
     if (threadIdx.x == SCAN_BLOCK - 1) *total = sh[SCAN_BLOCK - 1];
 }
 
+// Writes the records of the words of one block.  The block's detections are
+// first listed in LDS in output order (word, bit), then written one per
+// thread, so that the reads of V are independent of each other; a block with
+// more detections than the list holds walks its words thread by thread.
+__device__ __forceinline__ void emit_one(const float *__restrict__ V, int64_t pitch, int64_t plane_stride, int H,
+                                         int ntx, unsigned word, int b, const unsigned long long *__restrict__ pmask,
+                                         fdvm_blob *__restrict__ out, int idx, int cap) {
+    if (idx >= cap) return;
+    const unsigned sy = word / (unsigned)ntx;                  // word = (s * H + y) * ntx + tx
+    const int tx = (int)(word - sy * (unsigned)ntx);
+    const int s = (int)(sy / (unsigned)H);
+    const int y = (int)(sy - (unsigned)s * (unsigned)H);
+    const int xx = tx * DT_W + b;
+    const float v = V[(int64_t)s * plane_stride + (int64_t)y * pitch + xx];
+    fdvm_blob rec;
+    rec.y = y;
+    rec.x = xx;
+    rec.scale = s;
+    rec.polarity = pmask ? (((pmask[word] >> b) & 1ull) ? 1 : -1) : (v < 0.0f ? 1 : -1);
+    rec.value = v;
+    out[idx] = rec;
+}
+
+constexpr int EMIT_LIST = 2048;   // detections per block listed in LDS
+
 __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *__restrict__ V, int64_t pitch,
                                                                    int64_t plane_stride, int H, int W, int ntx,
                                                                    const unsigned long long *__restrict__ mask,
@@ -313,7 +381,9 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
                                                                    int64_t nwords, const int *__restrict__ boff,
                                                                    fdvm_blob *__restrict__ out, int cap) {
     constexpr int NW = SUM_THREADS * SUM_WORDS;
+    static_assert(NW <= (1 << 26), "word index in a list entry");
     __shared__ unsigned long long wbuf[NW];
+    __shared__ uint32_t list[EMIT_LIST];   // (word in block << 6) | bit
     __shared__ int part[SUM_THREADS / 64];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -334,34 +404,40 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
     }
     if (lane == 63) part[wv] = incl;
     __syncthreads();
-    int before = 0;
-    for (int i = 0; i < wv; ++i) before += part[i];
-    int idx = boff[blockIdx.x] + before + incl - c;
-    if (c == 0) return;
-    for (int i = 0; i < SUM_WORDS; ++i) {
-        unsigned long long bits = wbuf[first + i];
-        if (!bits) continue;
-        const unsigned word = (unsigned)(bbase + first + i);  // = (s * H + y) * ntx + tx
-        const unsigned sy = word / (unsigned)ntx;
-        const int tx = (int)(word - sy * (unsigned)ntx);
-        const int s = (int)(sy / (unsigned)H);
-        const int y = (int)(sy - (unsigned)s * (unsigned)H);
-        const unsigned long long pbits = pmask ? pmask[bbase + first + i] : 0ull;
-        while (bits) {
-            const int b = __ffsll((long long)bits) - 1;
-            bits &= bits - 1;
-            if (idx < cap) {
-                const int xx = tx * DT_W + b;
-                const float v = V[(int64_t)s * plane_stride + (int64_t)y * pitch + xx];
-                fdvm_blob rec;
-                rec.y = y;
-                rec.x = xx;
-                rec.scale = s;
-                rec.polarity = pmask ? (((pbits >> b) & 1ull) ? 1 : -1) : (v < 0.0f ? 1 : -1);
-                rec.value = v;
-                out[idx] = rec;
+    int before = 0, total = 0;
+    for (int i = 0; i < SUM_THREADS / 64; ++i) {
+        before += i < wv ? part[i] : 0;
+        total += part[i];
+    }
+    const int local = before + incl - c;   // this thread's first record within the block
+    const int base = boff[blockIdx.x];
+    if (total == 0) return;                // block-uniform
+    if (total <= EMIT_LIST) {
+        int li = local;
+        for (int i = 0; i < SUM_WORDS; ++i) {
+            unsigned long long bits = wbuf[first + i];
+            while (bits) {
+                const int b = __ffsll((long long)bits) - 1;
+                bits &= bits - 1;
+                list[li++] = ((uint32_t)(first + i) << 6) | (uint32_t)b;
             }
-            ++idx;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < total; t += SUM_THREADS) {
+            const uint32_t e = list[t];
+            emit_one(V, pitch, plane_stride, H, ntx, (unsigned)(bbase + (e >> 6)), (int)(e & 63u), pmask, out,
+                     base + t, cap);
+        }
+    } else {
+        int idx = base + local;
+        for (int i = 0; i < SUM_WORDS; ++i) {
+            unsigned long long bits = wbuf[first + i];
+            while (bits) {
+                const int b = __ffsll((long long)bits) - 1;
+                bits &= bits - 1;
+                emit_one(V, pitch, plane_stride, H, ntx, (unsigned)(bbase + first + i), b, pmask, out, idx, cap);
+                ++idx;
+            }
         }
     }
 }
@@ -434,8 +510,12 @@ hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch,
     const DetectLayout d = detect_layout(H, W, nscales);
     unsigned long long *mask = static_cast<unsigned long long *>(ws);
     dim3 g1((unsigned)d.ntx, (unsigned)((H + DT_ROWS * DT_WAVES - 1) / (DT_ROWS * DT_WAVES)));
-    hipLaunchKernelGGL(detect_mask_kernel, g1, dim3(DT_WAVES * 64), 0, st, resp, pitch, plane_stride, nscales,
-                       (int)H, (int)W, tau, border, mask, d.ntx);
+    if (tau > 0.0f)
+        hipLaunchKernelGGL(detect_mask_kernel<true>, g1, dim3(DT_WAVES * 64), 0, st, resp, pitch, plane_stride,
+                           nscales, (int)H, (int)W, tau, border, mask, d.ntx);
+    else
+        hipLaunchKernelGGL(detect_mask_kernel<false>, g1, dim3(DT_WAVES * 64), 0, st, resp, pitch, plane_stride,
+                           nscales, (int)H, (int)W, tau, border, mask, d.ntx);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return launch_compact(resp, H, W, pitch, plane_stride, nscales, nullptr, out, cap, count, ws, st);

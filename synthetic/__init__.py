@@ -137,3 +137,49 @@ def batch_frames(count: int = 64, seed: int = 2):
 def normalised_frame(H: int, W: int, seed: int, nblobs: int | None = None) -> np.ndarray:
     """aerial_frame / 4095 as float64 in [0, 1]."""
     return aerial_frame(H, W, seed, nblobs).astype(np.float64) / 4095.0
+
+
+# The test pattern of the paper's Hessian figures (Section 5, Figs 6 and 7):
+# solid black ellipses on a white background, one column per semi-major axis
+# (4, 8, 16, 32, 64 px, left to right) and one row per orientation of the
+# major axis (0 to 45 degrees in equal steps, top to bottom).  The figures do
+# not give the cell sizes, the number of orientations or the rasterisation;
+# here every cell is 4 a wide and 256 px tall, there are 5 orientations, and a
+# pixel's value is its uncovered area fraction from 4 x 4 sub-samples.
+ELLIPSE_AXES = (4, 8, 16, 32, 64)
+ELLIPSE_ANGLES = (0.0, 11.25, 22.5, 33.75, 45.0)
+
+
+def ellipse_pattern(aspect: float = 2.0, axes=ELLIPSE_AXES, angles=ELLIPSE_ANGLES, row_height: int = 256,
+                    supersample: int = 4):
+    """Returns (image float64 [H, W] in [0, 1], list of (cy, cx, a, b, angle_deg)).
+    Semi-minor axis b = a / aspect."""
+    widths = [4 * a for a in axes]
+    H, W = row_height * len(angles), sum(widths)
+    img = np.ones((H, W))
+    ss = supersample
+    offs = (np.arange(ss) + 0.5) / ss - 0.5
+    items = []
+    for i, ang in enumerate(angles):
+        cy = float(i * row_height + row_height // 2)     # centres on pixel centres
+        x0 = 0
+        for a, w in zip(axes, widths):
+            cx = float(x0 + w // 2)
+            b = a / aspect
+            t = math.radians(ang)
+            c, s = math.cos(t), math.sin(t)
+            ry = int(math.ceil(a)) + 2
+            ys = np.arange(int(cy) - ry, int(cy) + ry + 2)
+            xs = np.arange(int(cx) - ry, int(cx) + ry + 2)
+            cover = np.zeros((len(ys), len(xs)))
+            for dy in offs:
+                for dx in offs:
+                    yy = ys[:, None] + dy - cy
+                    xx = xs[None, :] + dx - cx
+                    u = xx * c + yy * s       # along the major axis
+                    v = -xx * s + yy * c
+                    cover += (u * u) / (a * a) + (v * v) / (b * b) <= 1.0
+            img[ys[0]:ys[-1] + 1, xs[0]:xs[-1] + 1] -= cover / (ss * ss)
+            items.append((cy, cx, float(a), float(b), ang))
+            x0 += w
+    return img, items

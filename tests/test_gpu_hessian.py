@@ -19,10 +19,13 @@ torch = pytest.importorskip("torch")
 P = pytest.importorskip("paper_1912_07133_amd")
 
 
-def check(frame_dev, x64, sigmas, t1_frac, t2, border=1, order=3):
+def check(frame_dev, x64, sigmas, t1_frac, t2, border=1, order=3, t1_abs=None):
     B = filtering.blur_bank(x64, [design.repeated_pole(order, s) for s in sigmas])
-    refs = [shape.detect_hessian(B[s], sg, 0.0, None, border) for s, sg in enumerate(sigmas)]
-    t1 = t1_frac * max(float(np.max(r[1])) for r in refs)
+    if t1_abs is None:
+        refs = [shape.detect_hessian(B[s], sg, 0.0, None, border) for s, sg in enumerate(sigmas)]
+        t1 = t1_frac * max(float(np.max(r[1])) for r in refs)
+    else:
+        t1 = t1_abs
     det, nd = P.iir_hessian(frame_dev, sigmas, t1, t2, border, order=order)
     nd = nd.cpu().numpy().astype(np.float64)
     got = {(int(d["scale"]), int(d["y"]), int(d["x"])): int(d["polarity"]) for d in det}
@@ -79,3 +82,21 @@ def test_full_frame_sigma_ladder():
     x = torch.from_numpy(frame.view(np.int16)).cuda()
     n = check(x, frame.astype(np.float64), cfg["sigmas"], 0.002, 1.0)
     assert n > 50
+
+
+def test_ellipse_pattern_scale_selection():
+    """Section 5 (Figs 6 and 7): the ellipse test pattern (aspect 2), all five
+    scales lambda = 2 sigma = 4 .. 64 in one call, Threshold #1 = 0.035 and
+    Threshold #2 = 0.6: exactly one detection per ellipse whose semi-major
+    axis equals lambda, at its centre, dark polarity; and parity with the
+    oracle on the whole stack."""
+    say("case: hessian ellipse pattern 1280x496, 5 scales")
+    img, items = syn.ellipse_pattern(2.0)
+    sig = [lam / 2 for lam in syn.ELLIPSE_AXES]
+    x = torch.from_numpy(img.astype(np.float32)).cuda()
+    check(x, img.astype(np.float32).astype(np.float64), sig, None, 0.6, t1_abs=0.035)
+    det, _ = P.iir_hessian(x, sig, 0.035, 0.6, 1)
+    got = sorted((int(d["scale"]), int(d["y"]), int(d["x"]), int(d["polarity"])) for d in det)
+    exp = sorted((s, int(cy), int(cx), -1) for s, lam in enumerate(syn.ELLIPSE_AXES)
+                 for (cy, cx, a, b, ang) in items if a == lam)
+    assert got == exp

@@ -5,6 +5,7 @@ import math
 import numpy as np
 import pytest
 
+import synthetic as syn
 from oracle import design, filtering, shape
 
 
@@ -210,3 +211,24 @@ def test_hessian_newton_step_exact_on_quadratic():
     ys, xs = np.nonzero(mask2)
     assert (12, 9) in list(zip(ys.tolist(), xs.tolist()))
     assert all(math.hypot(xx - x0, yy - y0) < 0.75 for yy, xx in zip(ys, xs))
+
+
+def test_hessian_ellipse_pattern_scale_selection():
+    """Section 5 (Figs 6 and 7): on the ellipse test pattern (aspect 2) with
+    the repeated-pole blur at lambda = 2 sigma = 4 .. 64, one scale-invariant
+    Threshold #1 on sigma^4 |H| keeps the centres of the ellipses whose
+    semi-major axis equals lambda and none of the others; adding Threshold #2
+    on the Newton offset leaves exactly one pixel, the centre, per matched
+    ellipse."""
+    img, items = syn.ellipse_pattern(2.0)
+    for lam in syn.ELLIPSE_AXES:
+        sg = lam / 2
+        B = filtering.blur_2d(img, design.repeated_pole(3, sg))
+        mask1, *_ = shape.detect_hessian(B, sg, 0.035, None, 1)
+        for (cy, cx, a, b, ang) in items:
+            iy, ix = int(cy), int(cx)
+            hit = bool(mask1[iy - 2:iy + 3, ix - 2:ix + 3].any())
+            assert hit == (a == lam), (lam, a, ang)
+        mask2, *_ = shape.detect_hessian(B, sg, 0.035, 0.6, 1)
+        got = sorted(zip(*[v.tolist() for v in np.nonzero(mask2)]))
+        assert got == sorted((int(cy), int(cx)) for (cy, cx, a, b, ang) in items if a == lam), lam
