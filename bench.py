@@ -183,37 +183,21 @@ def run_precision_leg(P, syn, torch, np, dev, stream, log):
     """One 8192 x 8192 frame (generator seed 3, 3200 blobs, / 4095) stored as
     float16 and as bfloat16; coloured SG FIR of lengths 33, 65, 129, 257
     (sigma = K / 3, direct and Toeplitz/MFMA) and the K = 3 IIR at the same
-    sigmas.  Throughput per form, and per scale the largest relative error
-    against float64 direct 2-D sums on 16 sampled pixels, for the stored and
-    for the original input (the IIR's impulse response truncated at 30 sigma)."""
-    from oracle import design, filtering   # error reference only
-
+    sigmas.  Throughput per form; the outputs at 16 sampled pixels are kept
+    for the error figures, which the CPU-baseline leg computes against FP64
+    references (precision_errors)."""
     cfg = syn.PRECISION
     Ks = [(m - 1) // 2 for m in cfg["fir_lengths"]]
     sig = [k / 3 for k in Ks]
     orig = syn.normalised_frame(cfg["H"], cfg["W"], cfg["seed"], nblobs=cfg["nblobs"])
     rng = np.random.default_rng(5)
-    pts = [tuple(p) for p in rng.integers(0, cfg["H"], (16, 2))]
+    pts = [tuple(int(v) for v in p) for p in rng.integers(0, cfg["H"], (16, 2))]
     mpx = cfg["H"] * cfg["W"] * len(sig) / 1e6
-
-    def sampled(img, h):
-        K = (len(h) - 1) // 2
-        r = np.arange(-K, K + 1)
-        H, W = img.shape
-        return np.array([h @ img[np.ix_(np.clip(i - r, 0, H - 1), np.clip(j - r, 0, W - 1))] @ h for i, j in pts])
-
-    taps = {"fir": [design.colored_sg_taps(s, K=K) for s, K in zip(sig, Ks)]}
-    iir_h = []
-    for s in sig:
-        half = int(30 * s) + 8
-        iir_h.append(filtering.impulse_response_by_recursion(design.repeated_pole(3, s), half))
-    taps["iir"] = iir_h
     out = {"workload": cfg["name"], "scales": [round(s, 4) for s in sig], "fir_lengths": cfg["fir_lengths"],
-           "error": "max |gpu - fp64| / max |fp64| over 16 sampled pixels, per scale", "forms": {}}
+           "error": "max |gpu - fp64| / max |fp64| over 16 sampled pixels, per scale", "forms": {},
+           "_pts": pts, "_sig": sig, "_Ks": Ks, "_samples": {}}
     for kind, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
-        xt = torch.from_numpy(orig.astype(np.float32)).to(tdt)
-        deq = xt.float().numpy().astype(np.float64)
-        x = xt.to(dev)
+        x = torch.from_numpy(orig.astype(np.float32)).to(tdt).to(dev)
         runs = {"iir": lambda: P.blur_iir(x, sig, order=3),
                 "fir_direct": lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=P.FIR_DIRECT),
                 "fir_mfma": lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=P.FIR_TOEPLITZ_MFMA)}
@@ -228,20 +212,52 @@ def run_precision_leg(P, syn, torch, np, dev, stream, log):
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 3
             Bn = B.cpu().numpy()
+            out["_samples"][f"{kind}_{name}"] = [[float(Bn[s, i, j]) for i, j in pts] for s in range(len(sig))]
+            out["forms"][f"{kind}_{name}"] = {"ms": round(ms, 3), "value": round(mpx / (ms / 1e3), 1)}
+            del B
+        log(f"precision {kind}: " + ", ".join(f"{k.split('_', 1)[1]} {v['ms']:.2f} ms"
+                                            for k, v in out["forms"].items() if k.startswith(kind)))
+    return out
+
+
+def precision_errors(prec, syn, torch, np, log):
+    """Per scale, the largest relative error of the sampled GPU outputs of the
+    precision leg against float64 direct 2-D sums of the FP64 oracle's taps
+    (the IIR's impulse response truncated at 30 sigma), for the stored and for
+    the original input.  Part of the CPU-baseline leg."""
+    from oracle import design, filtering
+
+    cfg = syn.PRECISION
+    pts, sig, Ks = prec["_pts"], prec["_sig"], prec["_Ks"]
+    orig = syn.normalised_frame(cfg["H"], cfg["W"], cfg["seed"], nblobs=cfg["nblobs"])
+
+    def sampled(img, h):
+        K = (len(h) - 1) // 2
+        r = np.arange(-K, K + 1)
+        H, W = img.shape
+        return np.array([h @ img[np.ix_(np.clip(i - r, 0, H - 1), np.clip(j - r, 0, W - 1))] @ h for i, j in pts])
+
+    taps = {"fir": [design.colored_sg_taps(s, K=K) for s, K in zip(sig, Ks)],
+            "iir": [filtering.impulse_response_by_recursion(design.repeated_pole(3, s), int(30 * s) + 8)
+                    for s in sig]}
+    for kind, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
+        deq = torch.from_numpy(orig.astype(np.float32)).to(tdt).float().numpy().astype(np.float64)
+        for name in ("iir", "fir_direct", "fir_mfma"):
+            key = f"{kind}_{name}"
+            if key not in prec["_samples"]:
+                continue
             hs = taps["iir" if name == "iir" else "fir"]
             eq, eo = [], []
             for s in range(len(sig)):
-                g = np.array([Bn[s, i, j] for i, j in pts], dtype=np.float64)
+                g = np.array(prec["_samples"][key][s], dtype=np.float64)
                 rq, ro = sampled(deq, hs[s]), sampled(orig, hs[s])
                 eq.append(float(np.max(np.abs(g - rq)) / np.max(np.abs(rq))))
                 eo.append(float(np.max(np.abs(g - ro)) / np.max(np.abs(ro))))
-            out["forms"][f"{kind}_{name}"] = {"ms": round(ms, 3), "value": round(mpx / (ms / 1e3), 1),
-                                             "err_vs_stored": [float(f"{v:.3g}") for v in eq],
-                                             "err_vs_original": [float(f"{v:.3g}") for v in eo]}
-            del B
-        log(f"precision {kind}: " + ", ".join(f"{k.split('_', 1)[1]} {v['ms']:.2f} ms max err {max(v['err_vs_original']):.2e}"
-                                            for k, v in out["forms"].items() if k.startswith(kind)))
-    return out
+            prec["forms"][key]["err_vs_stored"] = [float(f"{v:.3g}") for v in eq]
+            prec["forms"][key]["err_vs_original"] = [float(f"{v:.3g}") for v in eo]
+        log(f"precision {kind} errors vs original: " +
+            ", ".join(f"{k.split('_', 1)[1]} {max(v['err_vs_original']):.2e}"
+                      for k, v in prec["forms"].items() if k.startswith(kind) and "err_vs_original" in v))
 
 
 def main() -> int:
@@ -254,6 +270,7 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-grad", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--no-butterworth", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (for PMC byte scaling)")
     args = ap.parse_args()
@@ -413,6 +430,33 @@ def main() -> int:
             log(f"FIR {name}: {fms:.4f} ms/step, {fir[name]['value']:.0f} Mpx*scales/s (blur {fper[0]:.3f} ms, "
                 f"{fir[name]['blur_useful_TFLOPs']} useful TFLOP/s)")
 
+    # ---------------- Butterworth form of the IIR step (Filter E blur, L_B = 4)
+    butterworth = None
+    if not args.no_butterworth:
+        def designs_bw():
+            filt = (P.Filter * S)()
+            for i, s in enumerate(sig):
+                check(L.fdvm_filter_design(P.IIR_BUTTERWORTH, 4, s, 0, ctypes.byref(filt[i]), None, 0), "design")
+            return filt
+
+        def bw_step(ev):
+            filt = designs_bw()
+            ev[0].record(stream)
+            check(L.fdvm_iir_laplacian(x.data_ptr(), P.U16, H, W, W, V.data_ptr(), W, H * W, filt, S,
+                                       P.BC_REPLICATE, ws_iir.data_ptr(), ws_iir.numel(), sp), "iir_laplacian")
+            ev[1].record(stream)
+            detect_into(ev[2])
+
+        steps_bw = max(10, args.steps // 4)
+        tot_bw, _, per_bw = timed(bw_step, 3, steps_bw, 3)
+        ms_bw = tot_bw / steps_bw
+        butterworth = {"blur": "Butterworth L_B = 4 (Filter E), omega_c = sqrt(2 ln 2) / sigma",
+                       "steps": steps_bw, "ms_per_step": round(ms_bw, 4), "value": round(mpx / (ms_bw / 1e3), 1),
+                       "iir_laplacian_ms": round(per_bw[0], 5), "detect_ms": round(per_bw[1], 5),
+                       "detections": int(count.item())}
+        log(f"Butterworth: {ms_bw:.4f} ms/step, {butterworth['value']:.0f} Mpx*scales/s, "
+            f"iir_laplacian {per_bw[0]:.4f} ms, detections {butterworth['detections']}")
+
     # ---------------- batch: 64 uneven frames x 12 scales
     batch = None
     if not args.no_batch:
@@ -455,6 +499,8 @@ def main() -> int:
                   "mismatches_outside_fragile": len(mism),
                   "ok": bool(vratio <= 1.0 and not mism and nfrag <= 0.05 * V_gpu.size)}
         log(f"cpu baseline {cpu['value']} Mpx*scales/s; parity {parity}")
+        if precision is not None:
+            precision_errors(precision, syn, torch, np, log)
 
     extra_copy = None
     if args.calibrate_copy:
@@ -487,7 +533,8 @@ def main() -> int:
         "fir": fir,
         "batch": batch,
         "grad": grad,
-        "precision": precision,
+        "butterworth": butterworth,
+        "precision": None if precision is None else {k: v for k, v in precision.items() if not k.startswith("_")},
         "kernels": {k: {"ms": round(v["ms"], 5), "GB/s": round(v["GB/s"], 1), "launches": v["kernels"]}
                     for k, v in kern.items()},
         "detections": n_det,

@@ -61,7 +61,9 @@ typedef enum {
     FDVM_IIR_REPEATED_POLE_DSIGMA = 3, /* d h / d sigma of that blur (K + 1
                                     cascade sections); fdvm_iir_pass only   */
     FDVM_FIR_COLORED_SG = 1,    /* Filter C, Section 4.2 (Eqs 20-22)          */
-    FDVM_FIR_GAUSSIAN = 2       /* Filter A, Eqs 9c and 11                    */
+    FDVM_FIR_GAUSSIAN = 2,      /* Filter A, Eqs 9c and 11                    */
+    FDVM_IIR_BUTTERWORTH = 4    /* Filter E, Section 4.4 (order L_B = 4: one
+                                   complex-conjugate pole pair per direction) */
 } fdvm_kind;
 
 typedef enum { FDVM_BC_REPLICATE = 0, FDVM_BC_ZERO = 1 } fdvm_boundary;
@@ -95,14 +97,16 @@ enum {
  */
 typedef struct {
     int32_t kind;      /* fdvm_kind                                          */
-    int32_t order;     /* IIR: K (2 or 3); FIR: half-length K                */
+    int32_t order;     /* IIR: K (2 or 3); Butterworth: L_B (4); FIR: half-length K */
     double sigma;      /* scale parameter (pixels)                           */
-    double p;          /* IIR: repeated pole exp(-1/sigma); FIR: 0           */
+    double p;          /* IIR: repeated pole exp(-1/sigma); Butterworth: real
+                          part of the pole; FIR: 0                           */
     double b0;         /* IIR: central coefficient; FIR: h(0)                */
     double bp[4];      /* IIR: forward numerator, bp[0] = 0                  */
     double ap[4];      /* IIR: forward denominator, ap[0] = 1                */
     double side_gain;  /* IIR: B+(1)/A+(1) = (1 - b0)/2 (steady-state gain)  */
-    double omega_c;    /* coloured SG: cutoff of Eq 21 (3/sigma); else 0     */
+    double omega_c;    /* coloured SG: cutoff of Eq 21 (3/sigma); Butterworth:
+                          analogue cutoff sqrt(2 ln 2)/sigma; else 0         */
     int32_t ntaps;     /* FIR: 2K + 1; IIR: 0                                */
     int32_t reserved;
 } fdvm_filter;
@@ -131,6 +135,13 @@ const char *fdvm_status_string(fdvm_status status);
  *     same pole (a k-fold section differentiates into sections k and k + 1).
  *     Usable in fdvm_iir_pass (axes 0 and 1); with the replicate extension the
  *     pass is the sigma derivative of the blur pass of the extended input.
+ *   kind = FDVM_IIR_BUTTERWORTH: order L_B = 4 (the blur of Filter E).  The
+ *     analogue prototype of Eq 25 with omega_c = sqrt(2 ln 2) / sigma (its
+ *     half-gain point matched to a Gaussian of scale sigma), discretised by
+ *     the bilinear transform; per direction one complex-conjugate pole pair.
+ *     Fills b0, bp = [0, b1, b2, 0], ap = [1, a1, a2, 0] of the three-term DE
+ *     (Eq A17 form), p = real part of the pole, omega_c.  sigma in
+ *     [0.5, 4096].
  *   kind = FDVM_FIR_COLORED_SG: Eq 20 solved in float64 with S from Eq 22,
  *     omega_c = 3/sigma and dc constraints rho = [1, 0] (D = 3); needs
  *     omega_c < pi (sigma > 3/pi), otherwise the stopband of Eq 21 is empty
@@ -156,7 +167,8 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
  *             out[s * plane_stride + y * out_pitch + x]; out_pitch >= W,
  *             plane_stride >= H * out_pitch.  Must not overlap `in`.
  *   filters   host array of nscales IIR designs (fdvm_filter_design output);
- *             each must be FDVM_IIR_REPEATED_POLE with the same order (2 or 3).
+ *             all FDVM_IIR_REPEATED_POLE with the same order (2 or 3), or all
+ *             FDVM_IIR_BUTTERWORTH (order 4).
  *   bc        boundary extension (see conventions).
  *   ws        device workspace of at least
  *             fdvm_workspace_bytes(FDVM_OP_BLUR_IIR, H, W, nscales, 0) bytes
@@ -197,7 +209,7 @@ fdvm_status fdvm_iir_pass(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
 
 /*
  * fdvm_iir_laplacian -- the IIR blur and the high-pass stage in one call:
- * writes V_s = sigma_s^2 (D20 + D02) of the repeated-pole blur B_s (Table I
+ * writes V_s = sigma_s^2 (D20 + D02) of the IIR blur B_s (Table I
  * d = 2 taps along x and along y, clamp-to-edge extension of B_s), i.e. what
  * fdvm_blur_iir followed by fdvm_highpass(FDVM_HP_LAPLACIAN, normalize = 1)
  * computes, without storing B_s: the Laplacian is formed in float64 from the
@@ -239,7 +251,8 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
 
 /*
  * fdvm_iir_hessian -- the paper's blob detector (Section 5, Eqs 26-27) on the
- * repeated-pole blur, fused like fdvm_iir_laplacian: per scale and pixel the
+ * IIR blur (repeated-pole or Butterworth designs), fused like
+ * fdvm_iir_laplacian: per scale and pixel the
  * Hessian H = [[D20, D11], [D11, D02]] of the blur B_s (Table I taps, d = 2
  * central second differences, D11 the d = 1 difference along x of the d = 1
  * difference along y, clamp-to-edge extension), formed in float64 from the
@@ -269,7 +282,8 @@ fdvm_status fdvm_iir_hessian(const void *in, fdvm_dtype dt, int64_t H, int64_t W
  *   back onto the first and last sample of every column and row,
  *   sum_m g(m) T(m) with T(m) = sum_{k>m} h(k).
  *   g, out: device float32 planes (pitch, plane stride as in fdvm_blur_iir;
- *   must not overlap).  filters: FDVM_IIR_REPEATED_POLE designs.  ws: device,
+ *   must not overlap).  filters: FDVM_IIR_REPEATED_POLE designs (Butterworth
+ *   designs return FDVM_EUNSUPPORTED).  ws: device,
  *   >= fdvm_workspace_bytes(FDVM_OP_BLUR_IIR_ADJOINT, H, W, nscales, 0).
  */
 fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,

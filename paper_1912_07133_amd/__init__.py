@@ -24,7 +24,10 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "fdvm.h")
 
 # enums (include/fdvm.h)
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EOVERFLOW, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
-IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN, IIR_REPEATED_POLE_DSIGMA = 0, 1, 2, 3
+IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN, IIR_REPEATED_POLE_DSIGMA, IIR_BUTTERWORTH = 0, 1, 2, 3, 4
+# `order` of the IIR calls: 2 or 3 (repeated pole, Filter D) or BUTTERWORTH
+# (the L_B = 4 Butterworth blur, Filter E)
+BUTTERWORTH = "butterworth"
 BC_REPLICATE, BC_ZERO = 0, 1
 U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
@@ -33,8 +36,8 @@ OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_P
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
 
-KINDS = {"iir": IIR_REPEATED_POLE, "sg": FIR_COLORED_SG, "colored_sg": FIR_COLORED_SG,
-         "gaussian": FIR_GAUSSIAN}
+KINDS = {"iir": IIR_REPEATED_POLE, "butterworth": IIR_BUTTERWORTH, "sg": FIR_COLORED_SG,
+         "colored_sg": FIR_COLORED_SG, "gaussian": FIR_GAUSSIAN}
 BOUNDARIES = {"replicate": BC_REPLICATE, "zero": BC_ZERO}
 
 
@@ -254,8 +257,14 @@ def iir_laplacian(x, sigmas: Sequence[float], order: int = 3, boundary: str = "r
 
 def iir_designs(sigmas: Sequence[float], order: int = 3, dsigma: bool = False):
     """ctypes array of fdvm_filter designs, one per scale (fdvm_filter_design);
-    dsigma: the sigma derivatives of the blurs instead."""
-    kind = IIR_REPEATED_POLE_DSIGMA if dsigma else IIR_REPEATED_POLE
+    order 2 or 3: repeated pole; BUTTERWORTH: the L_B = 4 Butterworth blur;
+    dsigma: the sigma derivatives of the (repeated-pole) blurs instead."""
+    if order == BUTTERWORTH:
+        if dsigma:
+            raise FdvmError(EUNSUPPORTED, "sigma derivative of the Butterworth blur")
+        kind, order = IIR_BUTTERWORTH, 4
+    else:
+        kind = IIR_REPEATED_POLE_DSIGMA if dsigma else IIR_REPEATED_POLE
     filt = (Filter * len(sigmas))()
     for i, s in enumerate(sigmas):
         _check(lib().fdvm_filter_design(kind, order, float(s), 0, ctypes.byref(filt[i]), None, 0),

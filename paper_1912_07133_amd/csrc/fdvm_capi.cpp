@@ -68,6 +68,23 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
         *out = f;
         return FDVM_OK;
     }
+    if (kind == FDVM_IIR_BUTTERWORTH) {
+        if (order != 4) return FDVM_EINVAL;
+        if (!(sigma >= 0.5 && sigma <= 4096.0)) return FDVM_ERANGE;
+        double wc, db[3], da[3];
+        const Cascade c = butterworth_realisation(sigma, &wc, db, da);
+        f.order = order;
+        f.p = c.p;
+        f.b0 = c.b0;
+        for (int m = 0; m < 3; ++m) {
+            f.bp[m] = db[m];
+            f.ap[m] = da[m];
+        }
+        f.side_gain = 0.5 * (1.0 - c.b0);
+        f.omega_c = wc;
+        *out = f;
+        return FDVM_OK;
+    }
     if (kind == FDVM_IIR_REPEATED_POLE) {
         if (order != 2 && order != 3) return FDVM_EINVAL;
         if (!(sigma >= 0.25 && sigma <= 4096.0)) return FDVM_ERANGE;
@@ -139,21 +156,27 @@ fdvm_status iir_params(const fdvm_filter *filters, int nscales, fdvm_boundary bc
     if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
     const int order = filters[0].order;
     const int kind = filters[0].kind;
-    if (order != 2 && order != 3) return FDVM_EINVAL;
-    if (kind != FDVM_IIR_REPEATED_POLE && !(allow_dsigma && kind == FDVM_IIR_REPEATED_POLE_DSIGMA))
-        return FDVM_EINVAL;
+    if (kind == FDVM_IIR_BUTTERWORTH) {
+        if (order != 4) return FDVM_EINVAL;
+    } else {
+        if (order != 2 && order != 3) return FDVM_EINVAL;
+        if (kind != FDVM_IIR_REPEATED_POLE && !(allow_dsigma && kind == FDVM_IIR_REPEATED_POLE_DSIGMA))
+            return FDVM_EINVAL;
+    }
     std::memset(prm, 0, sizeof(*prm));
     prm->nscales = nscales;
     prm->boundary = bc;
     for (int s = 0; s < nscales; ++s) {
         const fdvm_filter &f = filters[s];
         if (f.kind != kind || f.order != order) return FDVM_EINVAL;
-        if (!(f.sigma >= 0.25 && f.sigma <= 4096.0)) return FDVM_ERANGE;
-        const Cascade c = kind == FDVM_IIR_REPEATED_POLE ? cascade_realisation(order, f.sigma)
-                                                         : sigma_derivative_realisation(order, f.sigma);
+        if (!(f.sigma >= (kind == FDVM_IIR_BUTTERWORTH ? 0.5 : 0.25) && f.sigma <= 4096.0)) return FDVM_ERANGE;
+        const Cascade c = kind == FDVM_IIR_BUTTERWORTH     ? butterworth_realisation(f.sigma, nullptr, nullptr, nullptr)
+                          : kind == FDVM_IIR_REPEATED_POLE ? cascade_realisation(order, f.sigma)
+                                                           : sigma_derivative_realisation(order, f.sigma);
         prm->order = c.sections;
         IirScaleParams &q = prm->s[s];
         q.p = c.p;
+        q.pim = c.pim;
         q.b0 = c.b0;
         for (int k = 0; k < MAX_SECTIONS; ++k) {
             q.w[k] = c.w[k];
@@ -309,6 +332,7 @@ fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t 
     IirParams prm;
     st = iir_params(filters, nscales, bc, &prm);
     if (st != FDVM_OK) return st;
+    if (prm.order == CPAIR) return FDVM_EUNSUPPORTED;   // folded tails are built for real-pole sections
     if (!ws) return FDVM_EINVAL;
     const size_t ubytes = ((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255;
     if (ws_bytes < ubytes + iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;

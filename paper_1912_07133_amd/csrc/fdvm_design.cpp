@@ -8,6 +8,7 @@
 //  * Coloured Savitzky-Golay FIR (Section 4.2, Eqs 20-22) and sampled Gaussian
 //    FIR (Eqs 9c, 11).
 #include <cmath>
+#include <complex>
 #include <vector>
 
 #include "fdvm_internal.h"
@@ -120,6 +121,55 @@ Cascade cascade_realisation(int K, double sigma) {
         c.ss[k] = ss;
     }
     c.lnp = -1.0 / sigma;
+    return c;
+}
+
+// Butterworth blur, L_B = 4 (Section 4.4; the procedure of Eqs A26-A31 for
+// one fewer pole pair).  Prototype H(s) = 1 / (1 + (s / wc)^4) (Eq 25 with
+// L_B = 4), wc = sqrt(2 ln 2) / sigma, bilinear s = 2 (z - 1) / (z + 1).  The
+// left-half-plane poles s1, conj(s1) with s1 = wc (-1 + i) / sqrt(2) map to
+// p = (2 + s1) / (2 - s1) and conj(p) inside the unit circle, and
+//     H(z) = K0 z^-2 (1 + z)^4 / ((1 - p/z)(1 - p'/z)(1 - p z)(1 - p' z)),
+// K0 = |1 - p|^4 / 16 (unit dc gain).  Residues of H(z) z^(n-1) at p, p' (and
+// at 0 for n = 0) give the two-sided impulse response
+//     h(n) = 2 Re(R p^(|n| - 1)), |n| >= 1;   h(0) = 2 Re(R / p) + K0 / |p|^2,
+//     R = K0 (1 + p)^4 / ((p - p')(1 - p^2)(1 - |p|^2)).
+// 1 - p, Im p and 1 - |p|^2 are formed from s1 directly so that they keep full
+// relative precision at coarse scales (p close to 1).
+Cascade butterworth_realisation(double sigma, double *omega_c, double de_b[3], double de_a[3]) {
+    using cd = std::complex<double>;
+    const double wc = std::sqrt(2.0 * std::log(2.0)) / sigma;
+    const cd s1 = wc * cd(-1.0, 1.0) / std::sqrt(2.0);
+    const double den = std::norm(2.0 - s1);                   // |2 - s1|^2
+    const cd p = (2.0 + s1) / (2.0 - s1);
+    const cd omp = -2.0 * s1 / (2.0 - s1);                    // 1 - p
+    const double im2 = 2.0 * 4.0 * s1.imag() / den;           // 2 Im p = (p - p') / i
+    const double om2 = -8.0 * s1.real() / den;                // 1 - |p|^2
+    const double m2 = 1.0 - om2;
+    const double K0 = std::pow(std::abs(omp), 4) / 16.0;
+    const cd R = K0 * std::pow(1.0 + p, 4) / (cd(0.0, im2) * (omp * (1.0 + p)) * om2);
+    Cascade c{};
+    c.p = p.real();
+    c.pim = p.imag();
+    c.b0 = 2.0 * (R / p).real() + K0 / m2;
+    c.w[0] = 2.0 * R.real();
+    c.w[1] = -2.0 * R.imag();
+    const cd ss = 1.0 / omp;
+    c.ss[0] = ss.real();
+    c.ss[1] = ss.imag();
+    c.lnp = 0.5 * std::log(m2);   // log |p|
+    c.sections = CPAIR;
+    if (omega_c) *omega_c = wc;
+    if (de_b && de_a) {
+        // y+(n) = b1 x(n-1) + b2 x(n-2) - a1 y+(n-1) - a2 y+(n-2): the impulse
+        // response h(1) = b1, h(2) = b2 - a1 b1
+        de_a[0] = 1.0;
+        de_a[1] = -2.0 * p.real();
+        de_a[2] = m2;
+        de_b[0] = 0.0;
+        de_b[1] = 2.0 * R.real();
+        de_b[2] = 2.0 * (R * p).real() + de_a[1] * de_b[1];
+    }
     return c;
 }
 

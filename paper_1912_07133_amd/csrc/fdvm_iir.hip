@@ -58,11 +58,12 @@ constexpr int CT = 64;       // rows per column tile
 constexpr int COL_WPB = 4;   // wavefronts (tiles) per column work-group
 
 struct ScaleArgs {
-    double p, inv_p, b0, sig2;
+    double p, inv_p, b0, sig2;   // complex pair: p, inv_p are the real parts
+    double pim, inv_pim;         // complex pair: imaginary parts of p and 1/p
     double w[MAX_SECTIONS];
     double ss[MAX_SECTIONS];
-    double pbit[7];    // p^(2^k), k = 0..6
-    double pchunk[7];  // row pass: p^(C 2^k), k = 0..6
+    double pbit[7];    // real pole: p^(2^k), k = 0..6
+    double pchunk[7];  // real pole, row pass: p^(C 2^k), k = 0..6
 };
 
 struct Args {
@@ -113,49 +114,82 @@ __device__ __forceinline__ double read_lane_d(double v, int l) {
 }
 
 // ------------------------------------------------------------ recursion
+// Two realisations share the kernels, selected by K:
+//  * K = 2..4 real sections with the repeated pole p (states v_1..v_K):
+//      v_1(n) = p v_1(n-1) + x(n),  v_k(n) = p v_k(n-1) + v_{k-1}(n);
+//  * K = CPAIR, one complex section with pole p (Butterworth pole pair), held
+//    as the two real states (Re v, Im v):  v(n) = p v(n-1) + x(n).
+// In both cases y+(n) = sum_k w_k v_k(n-1) over the real states.
 template <int K>
-__device__ __forceinline__ double cas_out(const ScaleArgs &c, const double (&v)[K]) {
+__device__ __forceinline__ double cas_out(const ScaleArgs &c, const double (&v)[cascade_states(K)]) {
     double y = c.w[0] * v[0];
 #pragma unroll
-    for (int k = 1; k < K; ++k) y = fma(c.w[k], v[k], y);
+    for (int k = 1; k < cascade_states(K); ++k) y = fma(c.w[k], v[k], y);
     return y;
 }
 
 template <int K>
-__device__ __forceinline__ void cas_step(double p, double (&v)[K], double x) {
-    v[0] = fma(p, v[0], x);
+__device__ __forceinline__ void cas_step(const ScaleArgs &c, double (&v)[cascade_states(K)], double x) {
+    if constexpr (K == CPAIR) {
+        const double re = fma(c.p, v[0], fma(-c.pim, v[1], x));
+        v[1] = fma(c.p, v[1], c.pim * v[0]);
+        v[0] = re;
+    } else {
+        v[0] = fma(c.p, v[0], x);
 #pragma unroll
-    for (int k = 1; k < K; ++k) v[k] = fma(p, v[k], v[k - 1]);
+        for (int k = 1; k < K; ++k) v[k] = fma(c.p, v[k], v[k - 1]);
+    }
 }
 
 // one step back: the state before sample x, from the state after it
 template <int K>
-__device__ __forceinline__ void cas_unstep(double inv_p, double (&v)[K], double x) {
+__device__ __forceinline__ void cas_unstep(const ScaleArgs &c, double (&v)[cascade_states(K)], double x) {
+    if constexpr (K == CPAIR) {
+        const double d = v[0] - x;   // (d + i v1) / p
+        const double re = fma(d, c.inv_p, -v[1] * c.inv_pim);
+        v[1] = fma(v[1], c.inv_p, d * c.inv_pim);
+        v[0] = re;
+    } else {
 #pragma unroll
-    for (int k = K - 1; k >= 1; --k) v[k] = (v[k] - v[k - 1]) * inv_p;
-    v[0] = (v[0] - x) * inv_p;
-}
-
-// v <- A^n v + z, with pn = p^n:
-//   (A^n v)_k = p^n sum_{j <= k} C(n + k - j - 1, k - j) v_j
-template <int K>
-__device__ __forceinline__ void cas_advance_add(double pn, double n, double (&v)[K], const double (&z)[K]) {
-    static_assert(K >= 2 && K <= MAX_SECTIONS, "2 to 4 sections");
-    const double c1 = n, c2 = 0.5 * n * (n + 1.0);
-    const double a = v[0], b = v[1];
-    if constexpr (K == 4) {
-        const double c3 = c2 * (n + 2.0) * (1.0 / 3.0);
-        v[3] = fma(pn, fma(c3, a, fma(c2, b, fma(c1, v[2], v[3]))), z[3]);
+        for (int k = K - 1; k >= 1; --k) v[k] = (v[k] - v[k - 1]) * c.inv_p;
+        v[0] = (v[0] - x) * c.inv_p;
     }
-    if constexpr (K >= 3) v[2] = fma(pn, fma(c2, a, fma(c1, b, v[2])), z[2]);
-    v[1] = fma(pn, fma(c1, a, b), z[1]);
-    v[0] = fma(pn, a, z[0]);
 }
 
+// The zero-input transition over n samples, A^n.  Real pole: a = p^n, b = n,
+//   (A^n v)_k = p^n sum_{j <= k} C(n + k - j - 1, k - j) v_j;
+// complex pair: a + i b = p^n.
+struct Tr {
+    double a, b;
+};
+
+// v <- A^n v + z
 template <int K>
-__device__ __forceinline__ void set_zero(double (&v)[K]) {
+__device__ __forceinline__ void cas_advance_add(Tr t, double (&v)[cascade_states(K)],
+                                                const double (&z)[cascade_states(K)]) {
+    if constexpr (K == CPAIR) {
+        const double re = fma(t.a, v[0], fma(-t.b, v[1], z[0]));
+        v[1] = fma(t.a, v[1], fma(t.b, v[0], z[1]));
+        v[0] = re;
+    } else {
+        static_assert(K >= 2 && K <= MAX_SECTIONS, "2 to 4 sections");
+        const double pn = t.a, n = t.b;
+        const double c1 = n, c2 = 0.5 * n * (n + 1.0);
+        const double a = v[0], b = v[1];
+        if constexpr (K == 4) {
+            const double c3 = c2 * (n + 2.0) * (1.0 / 3.0);
+            v[3] = fma(pn, fma(c3, a, fma(c2, b, fma(c1, v[2], v[3]))), z[3]);
+        }
+        if constexpr (K >= 3) v[2] = fma(pn, fma(c2, a, fma(c1, b, v[2])), z[2]);
+        v[1] = fma(pn, fma(c1, a, b), z[1]);
+        v[0] = fma(pn, a, z[0]);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void set_zero(double (&v)[N]) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = 0.0;
+    for (int k = 0; k < N; ++k) v[k] = 0.0;
 }
 
 // p^n for 0 <= n < 128 from the binary powers
@@ -174,6 +208,45 @@ __device__ __forceinline__ double pow_chunks(const ScaleArgs &c, int m) {
     for (int k = 0; k < 7; ++k)
         if ((m >> k) & 1) r *= c.pchunk[k];
     return r;
+}
+
+// p^n of the complex pole, n >= 0 (wave-uniform), by repeated squaring
+__device__ __forceinline__ Tr cpow(const ScaleArgs &c, int n) {
+    double rr = 1.0, ri = 0.0, br = c.p, bi = c.pim;
+    for (; n > 0; n >>= 1) {
+        if (n & 1) {
+            const double t = fma(rr, br, -ri * bi);
+            ri = fma(rr, bi, ri * br);
+            rr = t;
+        }
+        const double t = fma(br, br, -bi * bi);
+        bi = 2.0 * br * bi;
+        br = t;
+    }
+    return {rr, ri};
+}
+
+// transitions over n < 128 samples, C m samples (m < 128), C 2^l samples
+template <int K>
+__device__ __forceinline__ Tr tr_n(const ScaleArgs &c, int n) {
+    if constexpr (K == CPAIR)
+        return cpow(c, n);
+    else
+        return {pow_bits(c, n), (double)n};
+}
+template <int K, int C>
+__device__ __forceinline__ Tr tr_chunks(const ScaleArgs &c, int m) {
+    if constexpr (K == CPAIR)
+        return cpow(c, C * m);
+    else
+        return {pow_chunks(c, m), (double)(C * m)};
+}
+template <int K, int C>
+__device__ __forceinline__ Tr tr_level(const ScaleArgs &c, int l) {
+    if constexpr (K == CPAIR)
+        return cpow(c, C << l);
+    else
+        return {c.pchunk[l], (double)(C << l)};
 }
 
 template <typename T>
@@ -207,10 +280,11 @@ template <int K, int C, int R, typename TIn, bool FX>
 __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     const TIn *__restrict__ in, int64_t in_pitch, void *__restrict__ out_v, int64_t out_pitch,
     int64_t plane_stride, int H, int W, int *__restrict__ rexp, Args a) {
+    constexpr int NS = cascade_states(K);   // real states per direction
     using Acc = std::conditional_t<FX, double, float>;
     constexpr int LP = C + 1;  // padded lane stride in LDS: conflict-free chunk reads
     __shared__ float buf[ROW_WPB][64 * LP];
-    __shared__ double tot[ROW_WPB][2][K];
+    __shared__ double tot[ROW_WPB][2][NS];
     __shared__ float rmax[ROW_WPB];
 
     const int lane = threadIdx.x & 63;
@@ -268,116 +342,113 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 
     for (int s = 0; s < a.nscales; ++s) {
         const ScaleArgs &cf = a.s[s];
-        const double p = cf.p;
         // ---- zero-state chunk states
-        double zf[K], zb[K];
+        double zf[NS], zb[NS];
         set_zero(zf);
         set_zero(zb);
 #pragma unroll
-        for (int j = 0; j < C; ++j) cas_step(p, zf, (double)xs[j]);
+        for (int j = 0; j < C; ++j) cas_step<K>(cf, zf, (double)xs[j]);
 #pragma unroll
-        for (int j = C - 1; j >= 0; --j) cas_step(p, zb, (double)xs[j]);
+        for (int j = C - 1; j >= 0; --j) cas_step<K>(cf, zb, (double)xs[j]);
 
-        double init_l[K], init_r[K];
+        double init_l[NS], init_r[NS];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < NS; ++k) {
             init_l[k] = a.boundary == FDVM_BC_REPLICATE ? x_first * cf.ss[k] : 0.0;
             init_r[k] = a.boundary == FDVM_BC_REPLICATE ? x_last * cf.ss[k] : 0.0;
         }
         // forward elements: chunk 0 absorbs the left start state
-        double sf[K];
+        double sf[NS];
 #pragma unroll
-        for (int k = 0; k < K; ++k) sf[k] = zf[k];
+        for (int k = 0; k < NS; ++k) sf[k] = zf[k];
         if (g == 0) {
-            double t[K];
+            double t[NS];
 #pragma unroll
-            for (int k = 0; k < K; ++k) t[k] = init_l[k];
-            cas_advance_add(cf.pchunk[0], (double)C, t, zf);
+            for (int k = 0; k < NS; ++k) t[k] = init_l[k];
+            cas_advance_add<K>(tr_level<K, C>(cf, 0), t, zf);
 #pragma unroll
-            for (int k = 0; k < K; ++k) sf[k] = t[k];
+            for (int k = 0; k < NS; ++k) sf[k] = t[k];
         }
         // backward elements: the chunk holding column W-1 absorbs the right
         // start state; chunks past the end contribute nothing
-        double sb[K];
+        double sb[NS];
 #pragma unroll
-        for (int k = 0; k < K; ++k) sb[k] = g > g_last ? 0.0 : zb[k];
+        for (int k = 0; k < NS; ++k) sb[k] = g > g_last ? 0.0 : zb[k];
         if (g == g_last) {
-            double t[K];
+            double t[NS];
 #pragma unroll
-            for (int k = 0; k < K; ++k) t[k] = init_r[k];
-            cas_advance_add(pow_bits(cf, nv), (double)nv, t, zb);
+            for (int k = 0; k < NS; ++k) t[k] = init_r[k];
+            cas_advance_add<K>(tr_n<K>(cf, nv), t, zb);
 #pragma unroll
-            for (int k = 0; k < K; ++k) sb[k] = t[k];
+            for (int k = 0; k < NS; ++k) sb[k] = t[k];
         }
         // ---- intra-wavefront inclusive scans (forward from the left,
         // backward from the right): S_l <- A^(C d) S_(l-d) + S_l
 #pragma unroll
         for (int lvl = 0; lvl < 6; ++lvl) {
             const int d = 1 << lvl;
-            const double pn = cf.pchunk[lvl];
-            const double n = (double)(C * d);
-            double tf[K], tb[K];
+            const Tr tl = tr_level<K, C>(cf, lvl);
+            double tf[NS], tb[NS];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 tf[k] = __shfl_up(sf[k], d, 64);
                 tb[k] = __shfl_down(sb[k], d, 64);
             }
-            cas_advance_add(pn, n, tf, sf);
-            cas_advance_add(pn, n, tb, sb);
+            cas_advance_add<K>(tl, tf, sf);
+            cas_advance_add<K>(tl, tb, sb);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 if (lane >= d) sf[k] = tf[k];
                 if (lane + d < 64) sb[k] = tb[k];
             }
         }
         // ---- across the R wavefronts of the row
-        double cwf[K], cwb[K];  // states entering this wavefront's segment
+        double cwf[NS], cwb[NS];  // states entering this wavefront's segment
         set_zero(cwf);
         set_zero(cwb);
         if constexpr (R > 1) {
             if (lane == 63) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) tot[wv][0][k] = sf[k];
+                for (int k = 0; k < NS; ++k) tot[wv][0][k] = sf[k];
             }
             if (lane == 0) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) tot[wv][1][k] = sb[k];
+                for (int k = 0; k < NS; ++k) tot[wv][1][k] = sb[k];
             }
             __syncthreads();
             const int base = wv - r;
-            const double pn = cf.pchunk[6];
-            const double n = (double)(C * 64);
+            const Tr tw = tr_level<K, C>(cf, 6);
             for (int q = 0; q < r; ++q) {
-                double z[K];
+                double z[NS];
 #pragma unroll
-                for (int k = 0; k < K; ++k) z[k] = tot[base + q][0][k];
-                cas_advance_add(pn, n, cwf, z);
+                for (int k = 0; k < NS; ++k) z[k] = tot[base + q][0][k];
+                cas_advance_add<K>(tw, cwf, z);
             }
             for (int q = R - 1; q > r; --q) {
-                double z[K];
+                double z[NS];
 #pragma unroll
-                for (int k = 0; k < K; ++k) z[k] = tot[base + q][1][k];
-                cas_advance_add(pn, n, cwb, z);
+                for (int k = 0; k < NS; ++k) z[k] = tot[base + q][1][k];
+                cas_advance_add<K>(tw, cwb, z);
             }
             __syncthreads();
-            double t1[K], t2[K];
+            double t1[NS], t2[NS];
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 t1[k] = cwf[k];
                 t2[k] = cwb[k];
             }
-            cas_advance_add(pow_chunks(cf, lane + 1), (double)(C * (lane + 1)), t1, sf);
-            cas_advance_add(pow_chunks(cf, 64 - lane), (double)(C * (64 - lane)), t2, sb);
+            cas_advance_add<K>(tr_chunks<K, C>(cf, lane + 1), t1, sf);
+            cas_advance_add<K>(tr_chunks<K, C>(cf, 64 - lane), t2, sb);
 #pragma unroll
-            for (int k = 0; k < K; ++k) {
+            for (int k = 0; k < NS; ++k) {
                 sf[k] = t1[k];
                 sb[k] = t2[k];
             }
         }
         // carry into each chunk: exclusive scans
-        double vf[K], vb[K];
+        double vf[NS], vb[NS];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < NS; ++k) {
             const double up = __shfl_up(sf[k], 1, 64);
             const double dn = __shfl_down(sb[k], 1, 64);
             vf[k] = lane == 0 ? cwf[k] : up;
@@ -393,20 +464,20 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         if (full_wave) {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
-                ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
-                cas_step(p, vb, (double)xs[j]);
+                ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out<K>(cf, vb));
+                cas_step<K>(cf, vb, (double)xs[j]);
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                ys[j] = (Acc)((double)ys[j] + cas_out(cf, vf));
-                cas_step(p, vf, (double)xs[j]);
+                ys[j] = (Acc)((double)ys[j] + cas_out<K>(cf, vf));
+                cas_step<K>(cf, vf, (double)xs[j]);
             }
         } else {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
                 if (j < nv) {
-                    ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out(cf, vb));
-                    cas_step(p, vb, (double)xs[j]);
+                    ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out<K>(cf, vb));
+                    cas_step<K>(cf, vb, (double)xs[j]);
                 } else {
                     ys[j] = (Acc)0;
                 }
@@ -414,8 +485,8 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 if (j < nv) {
-                    ys[j] = (Acc)((double)ys[j] + cas_out(cf, vf));
-                    cas_step(p, vf, (double)xs[j]);
+                    ys[j] = (Acc)((double)ys[j] + cas_out<K>(cf, vf));
+                    cas_step<K>(cf, vf, (double)xs[j]);
                 }
             }
         }
@@ -448,6 +519,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 template <int K, bool FX>
 __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m, int H, int W, int nty,
                                                                       double *__restrict__ st, Args a) {
+    constexpr int NS = cascade_states(K);
     const int lane = threadIdx.x & 63;
     const int ty = blockIdx.y * COL_WPB + wave_id();
     const int s = blockIdx.z;
@@ -455,7 +527,6 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m,
     if (ty >= nty) return;
     const int ccol = min(col, W - 1);
     const ScaleArgs &cf = a.s[s];
-    const double p = cf.p;
     const int y0 = ty * CT;
     static_assert(CT == 64, "one row scale per lane");
     const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
@@ -466,19 +537,19 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m,
         const uint32_t v = m.raw(s, min(y, H - 1), ccol);
         xs[j] = y < H ? v : 0u;  // zeros (in either format) after the last row
     }                            // leave the backward zero state exact
-    double zf[K], zb[K];
+    double zf[NS], zb[NS];
     set_zero(zf);
     set_zero(zb);
 #pragma unroll
-    for (int j = 0; j < CT; ++j) cas_step(p, zf, m.cvt(xs[j], read_lane_d(lsc, j)));
+    for (int j = 0; j < CT; ++j) cas_step<K>(cf, zf, m.cvt(xs[j], read_lane_d(lsc, j)));
 #pragma unroll
-    for (int j = CT - 1; j >= 0; --j) cas_step(p, zb, m.cvt(xs[j], read_lane_d(lsc, j)));
+    for (int j = CT - 1; j >= 0; --j) cas_step<K>(cf, zb, m.cvt(xs[j], read_lane_d(lsc, j)));
     if (col < W) {
-        double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + col;
+        double *o = st + ((int64_t)(s * nty + ty) * 2 * NS) * W + col;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < NS; ++k) {
             o[(int64_t)k * W] = zf[k];
-            o[(int64_t)(K + k) * W] = zb[k];
+            o[(int64_t)(NS + k) * W] = zb[k];
         }
     }
 }
@@ -491,6 +562,7 @@ constexpr int SCAN_T = 64;  // threads (columns) per scan work-group
 template <int K, bool FX>
 __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, int W, int nty,
                                                               double *__restrict__ st, Args a) {
+    constexpr int NS = cascade_states(K);
     constexpr int U = 8;  // tiles whose states are fetched together
     const int col = blockIdx.x * SCAN_T + threadIdx.x;
     const int s = blockIdx.y;
@@ -499,20 +571,20 @@ __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, 
     const ScaleArgs &cf = a.s[s];
     const bool rep = a.boundary == FDVM_BC_REPLICATE;
     const double xe = m.at(s, dir == 0 ? 0 : H - 1, col);
-    double *base = st + (int64_t)s * nty * 2 * K * W + (int64_t)dir * K * W + col;
-    const int64_t tstride = (int64_t)2 * K * W;
-    double c[K];
+    double *base = st + (int64_t)s * nty * 2 * NS * W + (int64_t)dir * NS * W + col;
+    const int64_t tstride = (int64_t)2 * NS * W;
+    double c[NS];
 #pragma unroll
-    for (int k = 0; k < K; ++k) c[k] = rep ? xe * cf.ss[k] : 0.0;
-    const double pt = cf.pbit[6];  // p^64
+    for (int k = 0; k < NS; ++k) c[k] = rep ? xe * cf.ss[k] : 0.0;
+    const Tr tt = tr_n<K>(cf, CT);  // A^64
     for (int i0 = 0; i0 < nty; i0 += U) {
-        double z[U][K];
+        double z[U][NS];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = i0 + u;
             const int ty = dir == 0 ? i : nty - 1 - i;
 #pragma unroll
-            for (int k = 0; k < K; ++k) z[u][k] = i < nty ? base[ty * tstride + (int64_t)k * W] : 0.0;
+            for (int k = 0; k < NS; ++k) z[u][k] = i < nty ? base[ty * tstride + (int64_t)k * W] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -520,9 +592,9 @@ __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, 
             if (i >= nty) break;
             const int ty = dir == 0 ? i : nty - 1 - i;
 #pragma unroll
-            for (int k = 0; k < K; ++k) base[ty * tstride + (int64_t)k * W] = c[k];
+            for (int k = 0; k < NS; ++k) base[ty * tstride + (int64_t)k * W] = c[k];
             const int len = min(CT, H - ty * CT);
-            cas_advance_add(len == CT ? pt : pow_bits(cf, len), (double)len, c, z[u]);
+            cas_advance_add<K>(len == CT ? tt : tr_n<K>(cf, len), c, z[u]);
         }
     }
 }
@@ -579,6 +651,7 @@ template <int K, int MODE, bool FX>
 __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
     Mid<FX> m, float *out, int64_t out_pitch, int64_t out_plane_stride, int H, int W, int nty, int ntx,
     const double *__restrict__ st, Args a, HessArgs hz) {
+    constexpr int NS = cascade_states(K);
     constexpr bool LAP = MODE != FIN_BLUR;   // second differences need the neighbour rows and columns
     constexpr int QT = 16;
     constexpr int NQ = CT / QT;
@@ -597,7 +670,6 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
     if (ty >= nty) return;
     const int ccol = min(max(col, 0), W - 1);
     const ScaleArgs &cf = a.s[s];
-    const double p = cf.p;
     const int y0 = ty * CT;
     const int y1 = min(y0 + CT, H);
     const int len = y1 - y0;
@@ -609,13 +681,13 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
         row_to_lds(m.ptr(s, y, ccol), lt + r * 64);
     }
     const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
-    double vf[K], ub[NQ][K];
+    double vf[NS], ub[NQ][NS];
     {
-        const double *o = st + ((int64_t)(s * nty + ty) * 2 * K) * W + ccol;
+        const double *o = st + ((int64_t)(s * nty + ty) * 2 * NS) * W + ccol;
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
+        for (int k = 0; k < NS; ++k) {
             vf[k] = o[(int64_t)k * W];
-            ub[NQ - 1][k] = o[(int64_t)(K + k) * W];
+            ub[NQ - 1][k] = o[(int64_t)(NS + k) * W];
         }
     }
     double sc_above = 1.0, sc_below = 1.0;
@@ -633,11 +705,11 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
     double t_bot = 0.0;
     if (LAP && y1 < H) {
         const double xb = m.cvt(lt[(len + R0) * 64 + lane], sc_below);
-        double u[K];
+        double u[NS];
 #pragma unroll
-        for (int k = 0; k < K; ++k) u[k] = ub[NQ - 1][k];
-        cas_unstep(cf.inv_p, u, xb);  // state before row y1 (from below)
-        t_bot = fma(cf.b0, xb, cas_out(cf, u));
+        for (int k = 0; k < NS; ++k) u[k] = ub[NQ - 1][k];
+        cas_unstep<K>(cf, u, xb);  // state before row y1 (from below)
+        t_bot = fma(cf.b0, xb, cas_out<K>(cf, u));
     }
 
     auto body = [&](auto full_tag) {
@@ -689,45 +761,45 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
 #pragma unroll
         for (int q = NQ - 1; q >= 1; --q) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) ub[q - 1][k] = ub[q][k];
+            for (int k = 0; k < NS; ++k) ub[q - 1][k] = ub[q][k];
             if (FULL || q * QT < len) {
                 load_q(q);
 #pragma unroll
                 for (int i = QT - 1; i >= 0; --i)
-                    if (valid(q * QT + i)) cas_step(p, ub[q - 1], xd[i]);
+                    if (valid(q * QT + i)) cas_step<K>(cf, ub[q - 1], xd[i]);
             }
         }
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             if (!(FULL || q * QT < len)) break;
             load_q(q);
-            double u[K];
+            double u[NS];
 #pragma unroll
-            for (int k = 0; k < K; ++k) u[k] = ub[q][k];
+            for (int k = 0; k < NS; ++k) u[k] = ub[q][k];
 #pragma unroll
             for (int i = QT - 1; i >= 0; --i) {
                 if (valid(q * QT + i)) {
-                    t[i] = fma(cf.b0, xd[i], cas_out(cf, u));
-                    cas_step(p, u, xd[i]);
+                    t[i] = fma(cf.b0, xd[i], cas_out<K>(cf, u));
+                    cas_step<K>(cf, u, xd[i]);
                 }
             }
             if constexpr (LAP) {
                 if (q == 0 && y0 > 0) {  // B of the row above the tile; u is u(y0)
                     const double xa = m.cvt(lt[lane], sc_above);
-                    const double ta = fma(cf.b0, xa, cas_out(cf, u));
-                    double v[K];
+                    const double ta = fma(cf.b0, xa, cas_out<K>(cf, u));
+                    double v[NS];
 #pragma unroll
-                    for (int k = 0; k < K; ++k) v[k] = vf[k];
-                    cas_unstep(cf.inv_p, v, xa);  // forward state before row y0-1
-                    bm = ta + cas_out(cf, v);
+                    for (int k = 0; k < NS; ++k) v[k] = vf[k];
+                    cas_unstep<K>(cf, v, xa);  // forward state before row y0-1
+                    bm = ta + cas_out<K>(cf, v);
                 }
             }
 #pragma unroll
             for (int i = 0; i < QT; ++i) {
                 const int j = q * QT + i;
                 if (valid(j)) {
-                    const double b = t[i] + cas_out(cf, vf);
-                    cas_step(p, vf, xd[i]);
+                    const double b = t[i] + cas_out<K>(cf, vf);
+                    cas_step<K>(cf, vf, xd[i]);
                     if constexpr (!LAP) {
                         if (wr) dst[(int64_t)(y0 + j) * out_pitch + col] = (float)b;
                     } else {
@@ -745,7 +817,7 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
         }
         if constexpr (LAP) {
             // the row below the tile: B(y1) = y-(y1) + b0 x(y1) + W v(y1 - 1)
-            const double bn = y1 < H ? t_bot + cas_out(cf, vf) : bc;
+            const double bn = y1 < H ? t_bot + cas_out<K>(cf, vf) : bc;
             emit(y1 - 1, bm, bc, bn);
         }
     };
@@ -757,13 +829,18 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
 
 // Upper bound on sum_n |h(n)| of the two-sided blur: the impulse response of
 // every cascade section v_k is non-negative with sum ss[k] = 1/(1-p)^k, so
-// sum |h| <= |b0| + 2 sum_k |w_k| ss[k].  Slightly enlarged against rounding.
+// sum |h| <= |b0| + 2 sum_k |w_k| ss[k].  Complex pair: |h(n)| = |2 Re(R p^(n-1))|
+// <= |w| |p|^(n-1) with |w| = 2 |R|, so sum |h| <= |b0| + 2 |w| / (1 - |p|).
+// Slightly enlarged against rounding.
 double l1_bound(const IirParams &prm) {
     double m = 0.0;
     for (int s = 0; s < prm.nscales; ++s) {
         const IirScaleParams &q = prm.s[s];
         double b = std::fabs(q.b0);
-        for (int k = 0; k < prm.order; ++k) b += 2.0 * std::fabs(q.w[k]) * q.ss[k];
+        if (prm.order == CPAIR)
+            b += 2.0 * std::hypot(q.w[0], q.w[1]) / (1.0 - std::hypot(q.p, q.pim));
+        else
+            for (int k = 0; k < prm.order; ++k) b += 2.0 * std::fabs(q.w[k]) * q.ss[k];
         m = std::fmax(m, b);
     }
     return m * (1.0 + 1e-9);
@@ -778,14 +855,17 @@ Args make_args(const IirParams &prm, int C) {
         const IirScaleParams &q = prm.s[s];
         ScaleArgs &d = a.s[s];
         d.p = q.p;
-        d.inv_p = 1.0 / q.p;
+        d.pim = q.pim;
+        const double m2 = q.p * q.p + q.pim * q.pim;   // |p|^2
+        d.inv_p = q.p / m2;
+        d.inv_pim = -q.pim / m2;
         d.b0 = q.b0;
         d.sig2 = q.sig2;
         for (int k = 0; k < MAX_SECTIONS; ++k) {
             d.w[k] = q.w[k];
             d.ss[k] = q.ss[k];
         }
-        for (int k = 0; k < 7; ++k) {
+        for (int k = 0; k < 7 && prm.order != CPAIR; ++k) {   // complex powers are formed in the kernels
             d.pbit[k] = std::exp((double)(1 << k) * q.lnp);
             d.pchunk[k] = std::exp((double)C * (double)(1 << k) * q.lnp);
         }
@@ -933,6 +1013,7 @@ hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int6
     }
     if (prm.order == 3) { FDVM_ROWS_DT(3) }
     if (prm.order == 2) { FDVM_ROWS_DT(2) }
+    if (prm.order == CPAIR) { FDVM_ROWS_DT(CPAIR) }
     if (prm.order == 4 && !rexp) {
         switch (dtype) {
             case FDVM_U16: return launch_rows_f32out<4, uint16_t>(in, H, W, in_pitch, out, out_pitch, plane_stride, prm, st);
@@ -948,7 +1029,7 @@ hipError_t launch_iir_rows(const void *in, int dtype, int64_t H, int64_t W, int6
 
 size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order) {
     const int64_t nty = (H + CT - 1) / CT;
-    return ((size_t)nscales * nty * 2 * order * W * sizeof(double) + 255) & ~(size_t)255;
+    return ((size_t)nscales * nty * 2 * cascade_states(order) * W * sizeof(double) + 255) & ~(size_t)255;
 }
 
 hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp, float *out,
@@ -969,6 +1050,9 @@ hipError_t launch_iir_cols_mode(const void *in, int64_t in_pitch, int64_t in_pla
     if (prm.order == 2)
         return launch_cols_k<2>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, mode, hp, prm,
                                 states, st);
+    if (prm.order == CPAIR)
+        return launch_cols_k<CPAIR>(in, in_pitch, in_plane_stride, rexp, out, H, W, pitch, plane_stride, mode, hp,
+                                    prm, states, st);
     if (prm.order == 4 && !rexp && mode != FIN_HESSIAN)
         return launch_cols_kx<4, false>(Mid<false>{in, in_pitch, in_plane_stride, nullptr}, out, H, W, pitch,
                                         plane_stride, mode, hp, prm, states, st);

@@ -24,6 +24,7 @@ void repeated_pole_de(int K, double p, double e, double *b0, double bp[4], doubl
 constexpr int MAX_SECTIONS = 4;  // K = 3 blur and its sigma derivative (4 sections)
 struct Cascade {
     double p;
+    double pim;   // imaginary part of the pole (complex pair), else 0
     double b0;
     double w[MAX_SECTIONS];
     double ss[MAX_SECTIONS];
@@ -31,6 +32,16 @@ struct Cascade {
     int sections;
 };
 Cascade cascade_realisation(int K, double sigma);
+// Butterworth blur of order L_B = 4 (Section 4.4): one complex first-order
+// section per direction, v(n) = p v(n-1) + x(n), y+(n) = 2 Re(R v(n-1)),
+// held as the two real states (Re v, Im v) with weights w = (2 Re R, -2 Im R)
+// and steady state ss = (Re, Im) of 1 / (1 - p); sections = CPAIR.
+// omega_c receives the analogue cutoff.  de_b / de_a receive the three-term
+// DE coefficients [0, b1, b2] / [1, a1, a2].
+constexpr int CPAIR = 1;   // `sections` value of a complex pole pair
+Cascade butterworth_realisation(double sigma, double *omega_c, double de_b[3], double de_a[3]);
+// number of real states of a realisation with `sections` (CPAIR: 2)
+constexpr int cascade_states(int sections) { return sections == CPAIR ? 2 : sections; }
 // d h / d sigma of the same blur: b0 -> d b0 / d sigma and, since
 // d/dp of a k-fold section is (k/p)(section k+1 - section k), a cascade of
 // K + 1 sections with the same pole.
@@ -42,7 +53,7 @@ int gaussian_taps(double sigma, int K, double *taps);
 
 // ---------------------------------------------------------------- kernels
 struct IirScaleParams {
-    double p, b0;
+    double p, pim, b0;
     double w[MAX_SECTIONS];
     double ss[MAX_SECTIONS];
     double lnp;
@@ -51,7 +62,7 @@ struct IirScaleParams {
 
 struct IirParams {
     int nscales;
-    int order;  // number of cascade sections (2 .. MAX_SECTIONS)
+    int order;  // number of cascade sections (2 .. MAX_SECTIONS), or CPAIR
     int boundary;  // fdvm_boundary
     int pad;
     IirScaleParams s[FDVM_MAX_SCALES];

@@ -212,3 +212,63 @@ def test_sigma_derivative_design_matches_difference_of_designs():
             h = 1e-5 * s
             num = (P.filter_design("iir", s + h, order)["b0"] - P.filter_design("iir", s - h, order)["b0"]) / (2 * h)
             assert abs(d.b0 - num) <= 1e-6 * abs(num) + 1e-12, (order, s)
+
+
+# ------------------------------------------------- Butterworth (Filter E)
+
+def _wc(sigma):
+    return math.sqrt(2.0 * math.log(2.0)) / sigma   # Section 4.4 scale tuning
+
+
+def test_butterworth_design_matches_filter_e():
+    """The library's closed-form design (poles of the bilinear prototype and
+    residues) at the Filter E cutoff reproduces the printed coefficients and
+    the oracle's Eq A17 decomposition of the same transfer function."""
+    wc = 0.1472
+    d = P.filter_design("butterworth", math.sqrt(2.0 * math.log(2.0)) / wc, order=4)
+    assert d["order"] == 4 and d["omega_c"] == pytest.approx(wc, rel=1e-15)
+    printed = {"b0": 0.0518, "bp": [0.0, 0.0513, -0.0420], "ap": [1.0, -1.7929, 0.8124]}   # Section 5, Filter E
+    tol = 0.5e-4 + 1e-4   # 4 printed decimals; the printed cutoff is itself rounded
+    assert abs(d["b0"] - printed["b0"]) <= tol
+    for m in range(3):
+        assert abs(d["bp"][m] - printed["bp"][m]) <= tol
+        assert abs(d["ap"][m] - printed["ap"][m]) <= tol
+    ref = design.butterworth(4, wc)
+    assert d["b0"] == pytest.approx(ref.b0, rel=1e-12)
+    for m in range(3):
+        assert d["bp"][m] == pytest.approx(ref.bp[m], rel=1e-12, abs=1e-15)
+        assert d["ap"][m] == pytest.approx(ref.ap[m], rel=1e-12, abs=1e-15)
+
+
+@pytest.mark.parametrize("sigma", [0.5, 1.3, 4.0, 20.0, 150.0, 2000.0])
+def test_butterworth_design_across_scales(sigma):
+    """Against the oracle's decomposition at every scale of the supported
+    range, and unit dc gain of the three-term DE: b0 + 2 B+(1)/A+(1) = 1."""
+    d = P.filter_design("butterworth", sigma, order=4)
+    ref = design.butterworth(4, _wc(sigma))
+    assert d["b0"] == pytest.approx(ref.b0, rel=1e-9)
+    for m in (1, 2):
+        assert d["ap"][m] == pytest.approx(ref.ap[m], rel=1e-12)
+        assert d["bp"][m] == pytest.approx(ref.bp[m], rel=1e-8, abs=1e-14)
+    den = 1.0 + d["ap"][1] + d["ap"][2]   # A+(1) = |1 - p|^2, small at coarse scales
+    side = (d["bp"][1] + d["bp"][2]) / den
+    assert d["b0"] + 2.0 * side == pytest.approx(1.0, abs=1e-13 / den)
+    assert d["side_gain"] == pytest.approx(side, rel=1e-7)
+
+
+def test_butterworth_design_errors_and_unsupported_calls():
+    L = P.lib()
+    f = P.Filter()
+    assert L.fdvm_filter_design(P.IIR_BUTTERWORTH, 3, 4.0, 0, ctypes.byref(f), None, 0) == P.EINVAL
+    assert L.fdvm_filter_design(P.IIR_BUTTERWORTH, 4, 0.4, 0, ctypes.byref(f), None, 0) == P.ERANGE
+    assert L.fdvm_filter_design(P.IIR_BUTTERWORTH, 4, 4.0, 0, ctypes.byref(f), None, 0) == P.OK
+    g = P.Filter()
+    assert L.fdvm_filter_design(P.IIR_REPEATED_POLE, 3, 4.0, 0, ctypes.byref(g), None, 0) == P.OK
+    a, b, ws = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000)
+    big = 1 << 40
+    mixed = (P.Filter * 2)(f, g)
+    assert L.fdvm_blur_iir(a, P.F32, 8, 8, 8, b, 8, 64, mixed, 2, 0, ws, big, None) == P.EINVAL
+    one = (P.Filter * 1)(f)
+    assert L.fdvm_blur_iir_adjoint(a, 8, 8, 8, 64, b, 8, 64, one, 1, 0, ws, big, None) == P.EUNSUPPORTED
+    with pytest.raises(P.FdvmError):
+        P.iir_designs([2.0], P.BUTTERWORTH, dsigma=True)
