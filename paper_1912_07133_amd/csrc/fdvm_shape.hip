@@ -83,6 +83,13 @@ __device__ __forceinline__ float lane_right(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
+__device__ __forceinline__ int xcd_logical_block(int hw, int n) {
+    constexpr int NX = 8;   // XCDs
+    const int xcd = hw % NX, slot = hw / NX;
+    const int q = n / NX, r = n % NX;
+    return xcd * q + min(xcd, r) + slot;
+}
+
 constexpr int DT_NPL = 4;  // planes in each wavefront's LDS ring (the one in use + 3 in flight)
 
 // copy 64 lanes x 4 bytes from global memory straight into LDS (lane n to
@@ -159,9 +166,16 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     __shared__ unsigned long long words[DT_WAVES][FDVM_MAX_SCALES * RB];
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int tx = blockIdx.x;
+    // hardware work-group ids go round-robin to the 8 XCDs (each with its own
+    // L2); give every XCD one contiguous run of tiles (column tile fastest) so
+    // that the halo columns and rows that neighbouring tiles share are fetched
+    // from HBM once
+    const int nby = (H + DT_ROWS * DT_WAVES - 1) / (DT_ROWS * DT_WAVES);
+    const int lb = xcd_logical_block(blockIdx.x, ntx * nby);
+    const int tx = lb % ntx;
+    const int by = lb / ntx;
     const int x = tx * DT_W - 1 + lane;           // lanes 1..62 are output columns
-    const int y0 = (blockIdx.y * DT_WAVES + wv) * RB;
+    const int y0 = (by * DT_WAVES + wv) * RB;
     if (y0 >= H) return;
     const bool xin = x >= 0 && x < W;
     const int cx = min(max(x, 0), W - 1);
@@ -509,7 +523,7 @@ hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch,
                          void *ws, hipStream_t st) {
     const DetectLayout d = detect_layout(H, W, nscales);
     unsigned long long *mask = static_cast<unsigned long long *>(ws);
-    dim3 g1((unsigned)d.ntx, (unsigned)((H + DT_ROWS * DT_WAVES - 1) / (DT_ROWS * DT_WAVES)));
+    dim3 g1((unsigned)(d.ntx * ((H + DT_ROWS * DT_WAVES - 1) / (DT_ROWS * DT_WAVES))));
     if (tau > 0.0f)
         hipLaunchKernelGGL(detect_mask_kernel<true>, g1, dim3(DT_WAVES * 64), 0, st, resp, pitch, plane_stride,
                            nscales, (int)H, (int)W, tau, border, mask, d.ntx);
