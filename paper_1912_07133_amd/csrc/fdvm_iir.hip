@@ -69,7 +69,8 @@ struct ScaleArgs {
 struct Args {
     int nscales;
     int boundary;
-    int pad0, pad1;
+    int direct;  // row pass: rows 16-byte aligned, lanes store their chunks directly
+    int pad1;
     double l1;  // upper bound on the l1 norm of every scale's 1-D blur
     ScaleArgs s[FDVM_MAX_SCALES];
 };
@@ -490,19 +491,35 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
                 }
             }
         }
-        // ---- back through LDS (as raw 32-bit words) to coalesced stores
-#pragma unroll
-        for (int j = 0; j < C; ++j) {
-            if constexpr (FX) {
-                // |ys 2^ex| < 2^31 by the choice of ex (finite inputs)
-                lds[lane * LP + j] = __int_as_float((int)rint(ldexp((double)ys[j], ex)));
-            } else {
-                lds[lane * LP + j] = ys[j];
-            }
-        }
-        wave_lds_sync();  // the segment in LDS belongs to this wavefront alone
         uint32_t *dst = static_cast<uint32_t *>(out_v) + (int64_t)s * plane_stride +
                         (int64_t)(row_ok ? row : 0) * out_pitch;
+        auto word = [&](int j) -> uint32_t {
+            if constexpr (FX)
+                return (uint32_t)(int)rint(ldexp((double)ys[j], ex));   // |ys 2^ex| < 2^31 by the choice of ex
+            else
+                return __float_as_uint(ys[j]);
+        };
+        if (a.direct) {
+            // 16-byte aligned rows: every lane stores its own C words as
+            // 16-byte vectors (each line is completed by neighbouring lanes
+            // of the same instructions)
+            if (row_ok) {
+                if (nv == C) {
+#pragma unroll
+                    for (int j = 0; j < C; j += 4)
+                        *reinterpret_cast<uint4 *>(dst + c0 + j) = make_uint4(word(j), word(j + 1), word(j + 2), word(j + 3));
+                } else {
+#pragma unroll
+                    for (int j = 0; j < C; ++j)
+                        if (j < nv) dst[c0 + j] = word(j);
+                }
+            }
+            continue;
+        }
+        // ---- back through LDS (as raw 32-bit words) to coalesced stores
+#pragma unroll
+        for (int j = 0; j < C; ++j) lds[lane * LP + j] = __uint_as_float(word(j));
+        wave_lds_sync();  // the segment in LDS belongs to this wavefront alone
 #pragma unroll 4
         for (int i = 0; i < C; ++i) {
             const int j = i * 64 + lane;
@@ -877,6 +894,7 @@ template <int K, int C, int R, typename T, bool FX>
 hipError_t launch_rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, void *out, int64_t out_pitch,
                          int64_t plane_stride, int *rexp, const IirParams &prm, hipStream_t st) {
     Args a = make_args(prm, C);
+    a.direct = ((uintptr_t)out % 16 == 0 && out_pitch % 4 == 0 && plane_stride % 4 == 0) ? 1 : 0;
     const int rows_per_block = ROW_WPB / R;
     dim3 grid((unsigned)((H + rows_per_block - 1) / rows_per_block));
     hipLaunchKernelGGL((iir_rows_kernel<K, C, R, T, FX>), grid, dim3(ROW_WPB * 64), 0, st,
