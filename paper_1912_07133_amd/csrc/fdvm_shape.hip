@@ -387,12 +387,15 @@ __device__ __forceinline__ void emit_one(const float *__restrict__ V, int64_t pi
 }
 
 constexpr int EMIT_LIST = 2048;   // detections per block listed in LDS
+constexpr int EMIT_PREFIX_BLOCKS = 4096;   // emit forms its own block offsets up to this many blocks
 
 __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *__restrict__ V, int64_t pitch,
                                                                    int64_t plane_stride, int H, int W, int ntx,
                                                                    const unsigned long long *__restrict__ mask,
                                                                    const unsigned long long *__restrict__ pmask,
                                                                    int64_t nwords, const int *__restrict__ boff,
+                                                                   const int *__restrict__ bsum,
+                                                                   int32_t *__restrict__ count,
                                                                    fdvm_blob *__restrict__ out, int cap) {
     constexpr int NW = SUM_THREADS * SUM_WORDS;
     static_assert(NW <= (1 << 26), "word index in a list entry");
@@ -424,7 +427,23 @@ __global__ __launch_bounds__(SUM_THREADS) void detect_emit_kernel(const float *_
         total += part[i];
     }
     const int local = before + incl - c;   // this thread's first record within the block
-    const int base = boff[blockIdx.x];
+    int base;
+    if (bsum) {
+        // few blocks: this block's offset is the sum of the totals of the
+        // blocks before it (read straight from the per-block totals, fixed
+        // order); the last block writes the total count
+        int acc = 0;
+        for (int i = threadIdx.x; i < (int)blockIdx.x; i += SUM_THREADS) acc += bsum[i];
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+        __syncthreads();   // part[] is reused
+        if (lane == 0) part[wv] = acc;
+        __syncthreads();
+        base = 0;
+        for (int i = 0; i < SUM_THREADS / 64; ++i) base += part[i];
+        if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *count = base + total;
+    } else {
+        base = boff[blockIdx.x];
+    }
     if (total == 0) return;                // block-uniform
     if (total <= EMIT_LIST) {
         int li = local;
@@ -510,11 +529,18 @@ hipError_t launch_compact(const float *resp, int64_t H, int64_t W, int64_t pitch
                        bsum);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, bsum, (int)d.nblocks, boff, count);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    // up to EMIT_PREFIX_BLOCKS blocks every emit block sums the totals before
+    // it itself (at most that many reads from L2 per block); beyond, a scan
+    // kernel forms the offsets
+    const bool in_emit = d.nblocks <= EMIT_PREFIX_BLOCKS;
+    if (!in_emit) {
+        hipLaunchKernelGGL(scan_counts_kernel, dim3(1), dim3(SCAN_BLOCK), 0, st, bsum, (int)d.nblocks, boff, count);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(detect_emit_kernel, dim3((unsigned)d.nblocks), dim3(SUM_THREADS), 0, st, resp, pitch,
-                       plane_stride, (int)H, (int)W, d.ntx, mask, pmask, d.nwords, boff, out, cap);
+                       plane_stride, (int)H, (int)W, d.ntx, mask, pmask, d.nwords, boff,
+                       in_emit ? bsum : nullptr, count, out, cap);
     return hipGetLastError();
 }
 

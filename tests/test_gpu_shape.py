@@ -78,3 +78,38 @@ def test_detect_nothing_and_large_tau():
     assert len(P.detect_blobs(V, 0.0, 1)) == 0
     V2 = torch.randn((2, 50, 60), device="cuda")
     assert len(P.detect_blobs(V2, 1e9, 1)) == 0
+
+
+def planted(S, H, W, n, seed):
+    """Zero planes with n isolated +-1 values (no two within one step in
+    scale, y and x; none on the one-pixel border): each is a strict extremum
+    with |V| = 1, and no other pixel is."""
+    rng = np.random.default_rng(seed)
+    taken = set()
+    pts = []
+    while len(pts) < n:
+        s, y, x = int(rng.integers(0, S)), int(rng.integers(1, H - 1)), int(rng.integers(1, W - 1))
+        if any((s + a, y + b, x + c) in taken for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)):
+            continue
+        taken.add((s, y, x))
+        pts.append((s, y, x, 1 if rng.random() < 0.5 else -1))
+    return sorted(pts)
+
+
+@pytest.mark.parametrize("S,H,W", [(4, 2048, 1024), (16, 16384, 1024)])
+@pytest.mark.parametrize("tau", [0.5, 0.0])
+def test_detect_planted_extrema_both_compaction_routes(S, H, W, tau):
+    """Planted isolated extrema: the list is exactly the planted pixels in
+    (scale, y, x) order, polarity +1 for the minima.  The first stack has few
+    word blocks (the emit kernel forms its block offsets), the second more
+    than 4096 (a separate scan forms them); tau = 0 takes the key path."""
+    say(f"case: planted extrema S={S} {H}x{W} tau={tau}")
+    pts = planted(S, H, W, 3000, S * 7 + H)
+    V = torch.zeros((S, H, W), dtype=torch.float32, device="cuda")
+    idx = torch.tensor([[s, y, x] for s, y, x, _ in pts], dtype=torch.long, device="cuda")
+    val = torch.tensor([-1.0 if pol > 0 else 1.0 for *_, pol in pts], dtype=torch.float32, device="cuda")
+    V[idx[:, 0], idx[:, 1], idx[:, 2]] = val
+    det = P.detect_blobs(V, tau, 1)
+    got = [(int(d["scale"]), int(d["y"]), int(d["x"]), int(d["polarity"])) for d in det]
+    assert got == pts
+    del V
