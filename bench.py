@@ -272,11 +272,12 @@ def main() -> int:
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-butterworth", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a plain 256 MiB device copy (for PMC byte scaling)")
+                    help="report the plain 256 MiB device copy in the output (for PMC byte scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU; --gpus {args.gpus} is not supported "
-              "(frames and scales shard trivially across GPUs, see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              "(frames and scales are independent and would shard across GPUs without any exchange)",
+              file=sys.stderr)
         return 2
 
     import numpy as np

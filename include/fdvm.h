@@ -53,7 +53,7 @@ typedef enum {
     FDVM_ENOMEM = -3,       /* caller-provided buffer too small (taps, workspace) */
     FDVM_EDEVICE = -4,      /* a HIP call failed */
     FDVM_EOVERFLOW = -5,    /* more detections than the output capacity */
-    FDVM_EUNSUPPORTED = -6  /* valid request this build does not implement */
+    FDVM_EUNSUPPORTED = -6  /* valid request the library does not implement  */
 } fdvm_status;
 
 typedef enum {
