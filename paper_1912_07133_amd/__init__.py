@@ -501,15 +501,15 @@ def _make_iir_laplacian_fn():
 
         @staticmethod
         def forward(ctx, x, sigma, order=3, boundary="replicate"):
-            sig = [float(v) for v in sigma.detach().cpu().tolist()]
+            sig = _host_values(sigma)
             V = iir_laplacian(x.detach(), sig, order=order, boundary=boundary)
-            ctx.save_for_backward(x, V)
+            ctx.save_for_backward(x, V, sigma.detach())
             ctx.sig, ctx.order, ctx.boundary = sig, order, boundary
             return V
 
         @staticmethod
         def backward(ctx, gV):
-            x, V = ctx.saved_tensors
+            x, V, s = ctx.saved_tensors
             sig = ctx.sig
             gV = gV.contiguous().float()
             gB = laplacian_adjoint(gV, sig)
@@ -518,14 +518,33 @@ def _make_iir_laplacian_fn():
                 gx = blur_iir_adjoint(gB, sig, ctx.order, ctx.boundary).sum(0)
             if ctx.needs_input_grad[1]:
                 D1, D2 = dblur_dsigma_parts(x.detach(), sig, ctx.order, ctx.boundary)
-                s = torch.tensor(sig, dtype=torch.float64, device=V.device)
-                gsig = 2.0 / s * plane_dots(gV, V) + plane_dots(gB, D1) + plane_dots(gB, D2)
+                dots = 2.0 / s.to(device=V.device, dtype=torch.float64) * plane_dots(gV, V)
+                gsig = (dots + plane_dots(gB, D1) + plane_dots(gB, D2)).to(s.device)
             return gx, gsig, None, None
 
     return IirLaplacianFn
 
 
 _iir_lap_fn = None
+_sigma_cache = None
+
+
+def _host_values(sigma):
+    """The scales as Python floats (they become kernel arguments).  A device
+    tensor is copied to the host once per object and in-place version, so a
+    loop over frames with the same scales does not synchronise per frame."""
+    global _sigma_cache
+    import weakref
+    if _sigma_cache is None:
+        _sigma_cache = {}
+    hit = _sigma_cache.get(id(sigma))
+    if hit is not None and hit[0]() is sigma and hit[1] == sigma._version:
+        return hit[2]
+    vals = [float(v) for v in sigma.detach().cpu().tolist()]
+    if len(_sigma_cache) > 64:
+        _sigma_cache = {k: v for k, v in _sigma_cache.items() if v[0]() is not None}
+    _sigma_cache[id(sigma)] = (weakref.ref(sigma), sigma._version, vals)
+    return vals
 
 
 def iir_laplacian_grad(x, sigma, order: int = 3, boundary: str = "replicate"):

@@ -7,14 +7,16 @@
 //    swap roles, h being symmetric) and fold what lands outside [0, N) back
 //    onto the end samples.  The folded amounts are
 //        sum_{n<0} (h * g)(n) = sum_m g(m) T(m),  T(m) = sum_{k>m} h(k),
-//    and the mirror image at N - 1.  fold_kernel adds them, generating T(m)
-//    from T(0) = (1 - b0) / 2 and T(m) = T(m-1) - h(m), h(m) from the impulse
-//    response of the cascade sections.  With the zero extension G^T is the
+//    and the mirror image at N - 1.  fold_table_kernel tabulates T(m) per
+//    scale (T(0) = (1 - b0) / 2, T(m) = T(m-1) - h(m), h from the impulse
+//    response of the cascade sections); fold_cols_kernel / fold_rows_kernel
+//    form the two dot products of every column / row and add them.  With the zero extension G^T is the
 //    zero-start pass itself.
 //  * Scale-normalised Laplacian V = sigma^2 (D20 + D02) with the replicate
 //    extension of B (the Table I d = 2 taps along x and y): its transpose at
 //    (y, x) gathers g from the samples whose clamped neighbours are (y, x).
 //  * Plane inner products <a_s, b_s> in float64, fixed order (deterministic).
+#include <algorithm>
 #include <cmath>
 
 #include "fdvm_internal.h"
@@ -23,7 +25,7 @@ namespace fdvm {
 namespace {
 
 struct FoldScale {
-    double p, b0;
+    double lnp, b0;
     double w[MAX_SECTIONS];
     int mtail;  // T(m) is negligible from here on
     int pad;
@@ -33,48 +35,123 @@ struct FoldArgs {
     FoldScale s[FDVM_MAX_SCALES];
 };
 
-// AXIS 1 (y): thread = column x of plane s; AXIS 0 (x): thread = row y.
-// Adds the folded tails of `src` to the end samples of `dst`.
-template <int AXIS>
-__global__ __launch_bounds__(256) void fold_kernel(const float *__restrict__ src, int64_t src_pitch,
-                                                   int64_t src_plane, float *__restrict__ dst, int64_t dst_pitch,
-                                                   int64_t dst_plane, int H, int W, FoldArgs a) {
-    const int t = blockIdx.x * 256 + threadIdx.x;
-    const int s = blockIdx.y;
-    const int lines = AXIS == 1 ? W : H;   // columns or rows
-    const int N = AXIS == 1 ? H : W;       // samples along the folded axis
-    if (t >= lines) return;
+constexpr int TAB_T = 1024;   // threads of the table kernel (one block per scale)
+constexpr int FOLD_WAVES = 16;  // waves splitting the samples of a 64-column strip
+
+// T_s(m) for m < min(len, mtail): T(0) = (1 - b0) / 2 (half the off-centre
+// mass), T(m) = T(m-1) - h(m).  For lags n >= 0 the cascade's causal
+// response is h(n + 1) = sum_k w_k C(n + k, k) p^n (k + 1 repeated poles at
+// p), so every h is formed on its own and the running sum is a block scan
+// in float64, in a fixed order.
+__global__ __launch_bounds__(TAB_T) void fold_table_kernel(FoldArgs a, int len, int64_t stride,
+                                                           double *__restrict__ tab) {
+    __shared__ double wsum[TAB_T / 64];
+    const int s = blockIdx.x;
     const FoldScale &c = a.s[s];
-    const float *g = src + (int64_t)s * src_plane;
-    const int64_t step = AXIS == 1 ? src_pitch : 1;
-    const int64_t base = AXIS == 1 ? (int64_t)t : (int64_t)t * src_pitch;
-    const int M = min(N, c.mtail);
-    double u[MAX_SECTIONS];
-#pragma unroll
-    for (int k = 0; k < MAX_SECTIONS; ++k) u[k] = 1.0;   // sections' response at lag 0
-    double T = 0.5 * (1.0 - c.b0);                        // sum_{k >= 1} h(k)
-    double lo = 0.0, hi = 0.0;
-    for (int m = 0; m < M; ++m) {
-        lo = fma((double)g[base + (int64_t)m * step], T, lo);
-        hi = fma((double)g[base + (int64_t)(N - 1 - m) * step], T, hi);
-        // h(m + 1) = sum_k w_k u_k(m), then advance the sections one lag
-        double h = 0.0;
-#pragma unroll
-        for (int k = 0; k < MAX_SECTIONS; ++k)
-            if (k < a.sections) h = fma(c.w[k], u[k], h);
-        T -= h;
-        u[0] *= c.p;
-#pragma unroll
-        for (int k = 1; k < MAX_SECTIONS; ++k) u[k] = fma(c.p, u[k], u[k - 1]);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int M = min(len, c.mtail);
+    double carry = 0.5 * (1.0 - c.b0);
+    for (int m0 = 0; m0 < M; m0 += TAB_T) {
+        const int n = m0 + (int)threadIdx.x;
+        double binom = 1.0, h = c.w[0];
+        for (int k = 1; k < a.sections; ++k) {
+            binom *= (double)(n + k) / (double)k;
+            h = fma(c.w[k], binom, h);
+        }
+        h *= exp((double)n * c.lnp);  // h(n + 1)
+        double v = h;
+        for (int off = 1; off < 64; off <<= 1) {
+            const double t = __shfl_up(v, off, 64);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) wsum[wv] = v;
+        __syncthreads();
+        double pre = 0.0, tot = 0.0;
+        for (int i = 0; i < TAB_T / 64; ++i) {
+            if (i < wv) pre += wsum[i];
+            tot += wsum[i];
+        }
+        // sum_{j = m0+1}^{n} h(j) = (inclusive sum up to h(n + 1)) - h(n + 1)
+        if (n < M) tab[(int64_t)s * stride + n] = carry - ((pre + v) - h);
+        carry -= tot;
+        __syncthreads();
     }
-    float *d = dst + (int64_t)s * dst_plane;
-    const int64_t dstep = AXIS == 1 ? dst_pitch : 1;
-    const int64_t dbase = AXIS == 1 ? (int64_t)t : (int64_t)t * dst_pitch;
-    if (N == 1) {
-        d[dbase] = (float)((double)d[dbase] + lo + hi);
+}
+
+// Fold along y (axis 1): lane = column x of a 64-column strip, the waves of
+// the block split the samples m; their float64 partials are added in wave
+// order.  dst(0, x) += sum_m g(m, x) T(m), dst(H-1, x) += sum_m g(H-1-m, x) T(m).
+__global__ __launch_bounds__(64 * FOLD_WAVES) void fold_cols_kernel(const float *__restrict__ src,
+                                                                    int64_t src_pitch, int64_t src_plane,
+                                                                    float *__restrict__ dst, int64_t dst_pitch,
+                                                                    int64_t dst_plane, int H, int W, FoldArgs a,
+                                                                    const double *__restrict__ tab,
+                                                                    int64_t tab_stride) {
+    __shared__ double part[2][FOLD_WAVES][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int x = blockIdx.x * 64 + lane;
+    const int s = blockIdx.y;
+    const int M = min(H, a.s[s].mtail);
+    const float *g = src + (int64_t)s * src_plane + x;
+    const double *T = tab + (int64_t)s * tab_stride;
+    double lo = 0.0, hi = 0.0;
+    if (x < W) {
+        for (int m = wv; m < M; m += FOLD_WAVES) {
+            const double t = T[m];
+            lo = fma((double)g[(int64_t)m * src_pitch], t, lo);
+            hi = fma((double)g[(int64_t)(H - 1 - m) * src_pitch], t, hi);
+        }
+    }
+    part[0][wv][lane] = lo;
+    part[1][wv][lane] = hi;
+    __syncthreads();
+    if (wv != 0 || x >= W) return;
+    lo = 0.0;
+    hi = 0.0;
+    for (int i = 0; i < FOLD_WAVES; ++i) {
+        lo += part[0][i][lane];
+        hi += part[1][i][lane];
+    }
+    float *d = dst + (int64_t)s * dst_plane + x;
+    if (H == 1) {
+        d[0] = (float)((double)d[0] + lo + hi);
     } else {
-        d[dbase] = (float)((double)d[dbase] + lo);
-        d[dbase + (int64_t)(N - 1) * dstep] = (float)((double)d[dbase + (int64_t)(N - 1) * dstep] + hi);
+        d[0] = (float)((double)d[0] + lo);
+        d[(int64_t)(H - 1) * dst_pitch] = (float)((double)d[(int64_t)(H - 1) * dst_pitch] + hi);
+    }
+}
+
+// Fold along x (axis 0): one wave per row y; lanes stride the samples, the
+// wave sum is a fixed butterfly.
+__global__ __launch_bounds__(256) void fold_rows_kernel(const float *__restrict__ src, int64_t src_pitch,
+                                                        int64_t src_plane, float *__restrict__ dst,
+                                                        int64_t dst_pitch, int64_t dst_plane, int H, int W,
+                                                        FoldArgs a, const double *__restrict__ tab,
+                                                        int64_t tab_stride) {
+    const int lane = threadIdx.x & 63;
+    const int y = blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+    const int s = blockIdx.y;
+    if (y >= H) return;  // uniform per wave
+    const int M = min(W, a.s[s].mtail);
+    const float *g = src + (int64_t)s * src_plane + (int64_t)y * src_pitch;
+    const double *T = tab + (int64_t)s * tab_stride;
+    double lo = 0.0, hi = 0.0;
+    for (int m = lane; m < M; m += 64) {
+        const double t = T[m];
+        lo = fma((double)g[m], t, lo);
+        hi = fma((double)g[W - 1 - m], t, hi);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        lo += __shfl_xor(lo, off, 64);
+        hi += __shfl_xor(hi, off, 64);
+    }
+    if (lane != 0) return;
+    float *d = dst + (int64_t)s * dst_plane + (int64_t)y * dst_pitch;
+    if (W == 1) {
+        d[0] = (float)((double)d[0] + lo + hi);
+    } else {
+        d[0] = (float)((double)d[0] + lo);
+        d[W - 1] = (float)((double)d[W - 1] + hi);
     }
 }
 
@@ -140,15 +217,15 @@ __global__ __launch_bounds__(64) void dots_final_kernel(const double *__restrict
 
 }  // namespace
 
-hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, float *dst, int64_t dst_pitch,
-                       int64_t dst_plane, int64_t H, int64_t W, const IirParams &prm, int axis, hipStream_t st) {
+namespace {
+FoldArgs fold_args(const IirParams &prm) {
     FoldArgs a{};
     a.nscales = prm.nscales;
     a.sections = prm.order;
     for (int s = 0; s < prm.nscales; ++s) {
         const IirScaleParams &q = prm.s[s];
         FoldScale &f = a.s[s];
-        f.p = q.p;
+        f.lnp = q.lnp;
         f.b0 = q.b0;
         for (int k = 0; k < MAX_SECTIONS; ++k) f.w[k] = q.w[k];
         // p^m m^3 < 1e-20 beyond m = sigma (46 + 3 ln m); sigma = -1 / ln p
@@ -157,14 +234,34 @@ hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, f
         for (int it = 0; it < 4; ++it) m = sigma * (46.1 + 3.0 * std::log(m + 1.0)) + 8.0;
         f.mtail = (int)std::min(m, 2.0e9);
     }
-    const int lines = (int)(axis == 1 ? W : H);
-    dim3 grid((unsigned)((lines + 255) / 256), (unsigned)prm.nscales);
+    return a;
+}
+}  // namespace
+
+size_t fold_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    return ((size_t)std::max(H, W) * nscales * sizeof(double) + 255) & ~(size_t)255;
+}
+
+hipError_t launch_fold_table(int64_t H, int64_t W, const IirParams &prm, double *tab, hipStream_t st) {
+    const int64_t len = std::max(H, W);
+    hipLaunchKernelGGL(fold_table_kernel, dim3((unsigned)prm.nscales), dim3(TAB_T), 0, st, fold_args(prm),
+                       (int)len, len, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, float *dst, int64_t dst_pitch,
+                       int64_t dst_plane, int64_t H, int64_t W, const IirParams &prm, const double *tab, int axis,
+                       hipStream_t st) {
+    const FoldArgs a = fold_args(prm);
+    const int64_t tstride = std::max(H, W);
     if (axis == 1)
-        hipLaunchKernelGGL(fold_kernel<1>, grid, dim3(256), 0, st, src, src_pitch, src_plane, dst, dst_pitch,
-                           dst_plane, (int)H, (int)W, a);
+        hipLaunchKernelGGL(fold_cols_kernel, dim3((unsigned)((W + 63) / 64), (unsigned)prm.nscales),
+                           dim3(64 * FOLD_WAVES), 0, st, src, src_pitch, src_plane, dst, dst_pitch, dst_plane,
+                           (int)H, (int)W, a, tab, tstride);
     else
-        hipLaunchKernelGGL(fold_kernel<0>, grid, dim3(256), 0, st, src, src_pitch, src_plane, dst, dst_pitch,
-                           dst_plane, (int)H, (int)W, a);
+        hipLaunchKernelGGL(fold_rows_kernel, dim3((unsigned)((H + 3) / 4), (unsigned)prm.nscales), dim3(256), 0,
+                           st, src, src_pitch, src_plane, dst, dst_pitch, dst_plane, (int)H, (int)W, a, tab,
+                           tstride);
     return hipGetLastError();
 }
 

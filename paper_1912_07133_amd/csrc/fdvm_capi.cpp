@@ -137,7 +137,7 @@ size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_h
         case FDVM_OP_DETECT: return detect_workspace_bytes(H, W, nscales);
         case FDVM_OP_BLUR_IIR_ADJOINT:
             return (((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255) +
-                   iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS);
+                   iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS) + fold_workspace_bytes(H, W, nscales);
         case FDVM_OP_PLANE_DOTS: return dots_workspace_bytes(H, nscales);
         case FDVM_OP_IIR_HESSIAN:
             return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
@@ -335,16 +335,21 @@ fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t 
     if (prm.order == CPAIR) return FDVM_EUNSUPPORTED;   // folded tails are built for real-pole sections
     if (!ws) return FDVM_EINVAL;
     const size_t ubytes = ((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255;
-    if (ws_bytes < ubytes + iir_cols_workspace_bytes(H, W, nscales, prm.order)) return FDVM_ENOMEM;
+    const size_t sbytes = iir_cols_workspace_bytes(H, W, nscales, prm.order);
+    if (ws_bytes < ubytes + sbytes + fold_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
     if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
     hipStream_t hs = static_cast<hipStream_t>(stream);
     // G^T = (fold_x + zero-start x pass) (fold_y + zero-start y pass)
+    // ws: G_y^T g (pitch W) | column states | tail table T_s(m)
     IirParams zp = prm;
     zp.boundary = FDVM_BC_ZERO;
-    float *u = static_cast<float *>(ws);  // G_y^T g, pitch W
+    float *u = static_cast<float *>(ws);
     void *states = static_cast<char *>(ws) + ubytes;
+    double *tab = reinterpret_cast<double *>(static_cast<char *>(ws) + ubytes + sbytes);
     hipError_t e = launch_iir_cols(g, pitch, plane_stride, nullptr, u, H, W, W, H * W, false, zp, states, hs);
-    if (e == hipSuccess && bc == FDVM_BC_REPLICATE) e = launch_fold(g, pitch, plane_stride, u, W, H * W, H, W, prm, 1, hs);
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE) e = launch_fold_table(H, W, prm, tab, hs);
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
+        e = launch_fold(g, pitch, plane_stride, u, W, H * W, H, W, prm, tab, 1, hs);
     for (int s = 0; e == hipSuccess && s < nscales; ++s) {
         IirParams one = zp;
         one.nscales = 1;
@@ -353,7 +358,7 @@ fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t 
                             out_plane_stride, nullptr, 0, one, hs);
     }
     if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
-        e = launch_fold(u, W, H * W, out, out_pitch, out_plane_stride, H, W, prm, 0, hs);
+        e = launch_fold(u, W, H * W, out, out_pitch, out_plane_stride, H, W, prm, tab, 0, hs);
     return from_hip(e);
 }
 

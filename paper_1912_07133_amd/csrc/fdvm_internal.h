@@ -114,8 +114,13 @@ hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch,
 // Adjoint pieces (fdvm_adjoint.hip): fold of the replicate extension's
 // tails (axis 1: along y, axis 0: along x), transposed scale-normalised
 // Laplacian, per-plane float64 inner products.
+// tab: device float64, fold_workspace_bytes(H, W, nscales); written by
+// launch_fold_table, read by both folds.
+size_t fold_workspace_bytes(int64_t H, int64_t W, int nscales);
+hipError_t launch_fold_table(int64_t H, int64_t W, const IirParams &prm, double *tab, hipStream_t st);
 hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, float *dst, int64_t dst_pitch,
-                       int64_t dst_plane, int64_t H, int64_t W, const IirParams &prm, int axis, hipStream_t st);
+                       int64_t dst_plane, int64_t H, int64_t W, const IirParams &prm, const double *tab, int axis,
+                       hipStream_t st);
 hipError_t launch_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane, int nscales,
                                     const double *sigmas, float *out, int64_t out_pitch, int64_t out_plane,
                                     hipStream_t st);
