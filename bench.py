@@ -122,15 +122,23 @@ def run_batch_leg(P, syn, torch, np, dev, stream, log):
         b.run()
     t_graph = timed_ms(g.replay)
     same = bool(torch.equal(b.counts, eager_counts))
+    # algorithmic bytes of the batch: per frame the fused unit (frame read once,
+    # S intermediate planes written and read, S planes of V written) and the
+    # detection (S planes of V read), H W (2 + 16 S); far above the 256 MB
+    # Infinity Cache, so this is the HBM-bound figure
+    alg_bytes = sum(H * W for H, W, _ in specs) * (2 + 16 * S)
+    gbs = alg_bytes / (t_graph / 1e3) / 1e9
     out = {"workload": cfg["name"], "frames": len(specs), "scales": S, "mpx_scales": round(mpx_scales, 1),
            "per_frame_per_scale": {"ms": round(t_pfps, 3), "value": round(mpx_scales / (t_pfps / 1e3), 1)},
            "per_frame": {"ms": round(t_pf, 3), "value": round(mpx_scales / (t_pf / 1e3), 1)},
            "graph": {"ms": round(t_graph, 3), "value": round(mpx_scales / (t_graph / 1e3), 1), "lanes": nl,
                      "row_chunks": sorted({(int(f.shape[1]), int(c)) for f, c in zip(frames, chunks)}),
-                     "replay_counts_match_eager": same},
+                     "replay_counts_match_eager": same, "algorithmic_bytes": alg_bytes,
+                     "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
            "detections": int(b.counts.sum().item()), "unit": "Mpixel·scales/s"}
     log(f"batch: {mpx_scales:.0f} Mpx*scales; per frame+scale {t_pfps:.2f} ms, per frame {t_pf:.2f} ms, "
-        f"graph ({nl} lanes) {t_graph:.2f} ms = {out['graph']['value']:.0f} Mpx*scales/s")
+        f"graph ({nl} lanes) {t_graph:.2f} ms = {out['graph']['value']:.0f} Mpx*scales/s, "
+        f"{gbs:.0f} GB/s algorithmic ({100 * gbs / HBM_PEAK_GBS:.1f} % of 8 TB/s)")
     return out
 
 
