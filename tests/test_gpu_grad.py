@@ -32,8 +32,10 @@ def oracle_blur(x64, sigmas, bc="replicate"):
 
 
 @pytest.mark.parametrize("bc", ["replicate", "zero"])
-@pytest.mark.parametrize("shape_", [(70, 90), (1, 40), (33, 1), (130, 257)])
+@pytest.mark.parametrize("shape_", [(70, 90), (1, 40), (33, 1), (130, 257), (20, 2100), (1100, 7)])
 def test_blur_adjoint_dot_product(bc, shape_):
+    # the last two put more than 1024 samples of the folded tail (sigma = 40)
+    # along x and along y: the tail table is scanned in several blocks
     H, W = shape_
     say(f"case: blur adjoint {H}x{W} {bc}")
     rng = np.random.default_rng(H * 13 + W)
