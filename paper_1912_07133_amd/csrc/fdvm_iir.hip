@@ -287,6 +287,16 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     __shared__ float buf[ROW_WPB][64 * LP];
     __shared__ double tot[ROW_WPB][2][NS];
     __shared__ float rmax[ROW_WPB];
+    __shared__ ScaleArgs sargs[FDVM_MAX_SCALES];
+
+    // the scales' coefficients, copied once per work-group (a per-scale read
+    // of the kernel arguments is a chain of dependent scalar loads)
+    {
+        constexpr int NWD = sizeof(ScaleArgs) / sizeof(double);
+        const double *from = reinterpret_cast<const double *>(a.s);
+        double *to = reinterpret_cast<double *>(sargs);
+        for (int i = threadIdx.x; i < a.nscales * NWD; i += ROW_WPB * 64) to[i] = from[i];
+    }
 
     const int lane = threadIdx.x & 63;
     const int wv = wave_id();
@@ -321,11 +331,9 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o, 64));
         if (lane == 0) rmax[wv] = amax;
     }
-    // each wavefront stages its own segment; only the R > 1 exponent needs the others
-    if constexpr (R > 1 && FX)
-        __syncthreads();
-    else
-        wave_lds_sync();
+    // each wavefront stages its own segment; the R > 1 exponent needs the
+    // others' row maxima, and every wavefront needs the copied coefficients
+    __syncthreads();
     // fixed-point exponent of this row: |out| <= max|x| * l1 < 2^(ilogb + 1)
     int ex = 0;
     if constexpr (FX) {
@@ -342,7 +350,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     const bool full_wave = __all(nv == C);
 
     for (int s = 0; s < a.nscales; ++s) {
-        const ScaleArgs &cf = a.s[s];
+        const ScaleArgs &cf = sargs[s];
         // ---- zero-state chunk states
         double zf[NS], zb[NS];
         set_zero(zf);
