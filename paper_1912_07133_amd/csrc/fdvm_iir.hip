@@ -284,7 +284,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     constexpr int NS = cascade_states(K);   // real states per direction
     using Acc = std::conditional_t<FX, double, float>;
     constexpr int LP = C + 1;  // padded lane stride in LDS: conflict-free chunk reads
-    __shared__ float buf[ROW_WPB][64 * LP];
+    __shared__ __attribute__((aligned(16))) float buf[ROW_WPB][64 * LP];
     __shared__ double tot[ROW_WPB][2][NS];
     __shared__ float rmax[ROW_WPB];
     __shared__ ScaleArgs sargs[FDVM_MAX_SCALES];
@@ -508,20 +508,31 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
                 return __float_as_uint(ys[j]);
         };
         if (a.direct) {
-            // 16-byte aligned rows: every lane stores its own C words as
-            // 16-byte vectors (each line is completed by neighbouring lanes
-            // of the same instructions)
-            if (row_ok) {
-                if (nv == C) {
+            // 16-byte aligned rows.  Groups of NB = C / 4 lanes exchange their
+            // 16-byte blocks through this wavefront's LDS segment (an NB x NB
+            // transpose, XOR-swizzled against bank conflicts), so that every
+            // store instruction writes whole runs of 16 NB bytes; a group that
+            // reaches past the row's end stores its own words instead.
+            constexpr int NB = C / 4;
+            uint4 *l16 = reinterpret_cast<uint4 *>(lds);
+            const int gr = lane % NB;  // lane within its group
+            const int gl = lane - gr;  // first lane of the group
 #pragma unroll
-                    for (int j = 0; j < C; j += 4)
-                        *reinterpret_cast<uint4 *>(dst + c0 + j) = make_uint4(word(j), word(j + 1), word(j + 2), word(j + 3));
+            for (int i = 0; i < NB; ++i)
+                l16[lane * NB + (i ^ gr)] = make_uint4(word(4 * i), word(4 * i + 1), word(4 * i + 2), word(4 * i + 3));
+            wave_lds_sync();
+            if (row_ok) {
+                if (seg0 + (gl + NB) * C <= W) {
+#pragma unroll
+                    for (int i = 0; i < NB; ++i)
+                        *reinterpret_cast<uint4 *>(dst + seg0 + (gl + i) * C + 4 * gr) = l16[(gl + i) * NB + (gr ^ i)];
                 } else {
 #pragma unroll
                     for (int j = 0; j < C; ++j)
                         if (j < nv) dst[c0 + j] = word(j);
                 }
             }
+            wave_lds_sync();
             continue;
         }
         // ---- back through LDS (as raw 32-bit words) to coalesced stores
