@@ -11,6 +11,7 @@ works without the library, but every call raises if it is not built.
 from __future__ import annotations
 
 import ctypes
+import functools
 import math
 import os
 import re
@@ -258,7 +259,14 @@ def iir_laplacian(x, sigmas: Sequence[float], order: int = 3, boundary: str = "r
 def iir_designs(sigmas: Sequence[float], order: int = 3, dsigma: bool = False):
     """ctypes array of fdvm_filter designs, one per scale (fdvm_filter_design);
     order 2 or 3: repeated pole; BUTTERWORTH: the L_B = 4 Butterworth blur;
-    dsigma: the sigma derivatives of the (repeated-pole) blurs instead."""
+    dsigma: the sigma derivatives of the (repeated-pole) blurs instead.
+    Designs are pure functions of their arguments and the library only reads
+    them, so the arrays are memoised (callers must not modify them)."""
+    return _iir_designs_cached(tuple(float(s) for s in sigmas), order, bool(dsigma))
+
+
+@functools.lru_cache(maxsize=128)
+def _iir_designs_cached(sigmas, order, dsigma):
     if order == BUTTERWORTH:
         if dsigma:
             raise FdvmError(EUNSUPPORTED, "sigma derivative of the Butterworth blur")
@@ -267,8 +275,7 @@ def iir_designs(sigmas: Sequence[float], order: int = 3, dsigma: bool = False):
         kind = IIR_REPEATED_POLE_DSIGMA if dsigma else IIR_REPEATED_POLE
     filt = (Filter * len(sigmas))()
     for i, s in enumerate(sigmas):
-        _check(lib().fdvm_filter_design(kind, order, float(s), 0, ctypes.byref(filt[i]), None, 0),
-               "fdvm_filter_design")
+        _check(lib().fdvm_filter_design(kind, order, s, 0, ctypes.byref(filt[i]), None, 0), "fdvm_filter_design")
     return filt
 
 
