@@ -349,7 +349,11 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
     for (int j = 0; j < C; ++j) xs[j] = lds[lane * LP + j];
     const bool full_wave = __all(nv == C);
 
-    for (int s = 0; s < a.nscales; ++s) {
+    // wavefronts start at different scales so that their stores do not all
+    // arrive at once (the R wavefronts of a row step through the scales together)
+    const int rot = (R == 1 ? row : (int)blockIdx.x) % a.nscales;
+    for (int si = 0; si < a.nscales; ++si) {
+        const int s = si + rot < a.nscales ? si + rot : si + rot - a.nscales;
         const ScaleArgs &cf = sargs[s];
         // ---- zero-state chunk states
         double zf[NS], zb[NS];
