@@ -145,6 +145,20 @@ def test_fused_laplacian_ragged(shape, order):
         check_v(got, x64, sigmas, order, bc, bc)
 
 
+@pytest.mark.parametrize("shape", [(40, 1000), (24, 2100), (9, 5000)])
+def test_max_scale_count(shape):
+    """The most scales one call takes (wavefronts of the row pass start at
+    different scales), with one, two and three wavefronts per row."""
+    H, W = shape
+    say(f"case: {P.MAX_SCALES} scales {H}x{W}")
+    rng = np.random.default_rng(H * 17 + W)
+    img = rng.random((H, W)) * 100 + np.linspace(0, 20, W)[None, :]
+    sig = syn.geometric_scales(0.7, 90.0, P.MAX_SCALES)
+    x, x64 = to_dev(img, "f32")
+    assert_planes_close(P.blur_iir(x, sig, order=3).cpu().numpy(), oracle_bank(x64, sig, 3, "replicate"))
+    check_v(P.iir_laplacian(x, sig, order=3).cpu().numpy(), x64, sig, 3, "replicate", "max scales")
+
+
 def test_fused_laplacian_full_frame():
     cfg = syn.FULL_FRAME
     say("case: fused laplacian full frame 2048x2048 u16 8 scales")
