@@ -10,8 +10,8 @@
 //    and the mirror image at N - 1.  fold_table_kernel tabulates T(m) per
 //    scale (T(0) = (1 - b0) / 2, T(m) = T(m-1) - h(m), h from the impulse
 //    response of the cascade sections); fold_cols_kernel / fold_rows_kernel
-//    form the two dot products of every column / row and add them.  With the zero extension G^T is the
-//    zero-start pass itself.
+//    form the two dot products of every column / row and add them.  With the
+//    zero extension G^T is the zero-start pass itself.
 //  * Scale-normalised Laplacian V = sigma^2 (D20 + D02) with the replicate
 //    extension of B (the Table I d = 2 taps along x and y): its transpose at
 //    (y, x) gathers g from the samples whose clamped neighbours are (y, x).
