@@ -34,7 +34,7 @@
 // across the R wavefronts through LDS), outputs go back through LDS to
 // coalesced stores.  All S scales are computed from one staged copy of the row.
 //
-// Column pass (y), lane = column (coalesced along the row), 64-row tiles:
+// Column pass (y), lane = column (coalesced along the row), tiles of CT rows:
 //   states  -- every tile's zero-state end states (forward and backward);
 //   scan    -- per column, the states are chained into the true carries that
 //              enter every tile (forward from the top, backward from the bottom);
@@ -54,7 +54,8 @@ namespace fdvm {
 namespace {
 
 constexpr int ROW_WPB = 8;   // wavefronts per row-pass work-group
-constexpr int CT = 64;       // rows per column tile
+constexpr int CT = 48;       // rows per column tile (a multiple of 16, at most 64): 48 keeps the
+                             // final pass's LDS at 12.8 KB per wavefront, 12 wavefronts per CU
 constexpr int COL_WPB = 4;   // wavefronts (tiles) per column work-group
 
 struct ScaleArgs {
@@ -554,7 +555,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 }
 
 // ------------------------------------------------------------ column pass
-// (a) zero-state end states of every 64-row tile (float64).  st layout:
+// (a) zero-state end states of every CT-row tile (float64).  st layout:
 //     st[((s * nty + ty) * 2K + k) * W + x], k < K forward, k >= K backward.
 template <int K, bool FX>
 __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m, int H, int W, int nty,
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m,
     const int ccol = min(col, W - 1);
     const ScaleArgs &cf = a.s[s];
     const int y0 = ty * CT;
-    static_assert(CT == 64, "one row scale per lane");
+    static_assert(CT <= 64, "one row scale per lane");
     const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
     uint32_t xs[CT];
 #pragma unroll
@@ -672,18 +673,18 @@ __device__ __forceinline__ void row_to_lds(const void *g, uint32_t *l) {
 }
 __device__ __forceinline__ void wait_lds_dma() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// (c) final pass of one 64-row tile per wavefront.  LAP = false: writes the
+// (c) final pass of one CT-row tile per wavefront.  LAP = false: writes the
 // blur; in place is allowed (a tile reads and writes only its own rows, and it
 // stages all of them before its first write).  LAP = true: writes
 // sigma^2 (D20 + D02) of the blur; lanes cover columns x0 - 1 .. x0 + 62 and
 // lanes 1..62 write (in and out must not overlap).
 // The tile (plus the rows just above and below it for LAP) is first copied
 // into LDS with direct global-to-LDS loads, so the whole tile is in flight at
-// once and no registers hold it.  It is then finished in quarters of 16 rows
-// so that only 16 float64 partial outputs are live: one backward sweep over the
-// lower three quarters records the state entering each quarter from below;
-// then every quarter, top first, is swept backwards from its recorded state
-// and finished by the forward sweep, which runs through the whole tile.
+// once and no registers hold it.  It is then finished in bands of 16 rows
+// (QT) so that only 16 float64 partial outputs are live: one backward sweep
+// over all bands but the first records the state entering each band from
+// below; then every band, top first, is swept backwards from its recorded
+// state and finished by the forward sweep, which runs through the whole tile.
 constexpr int FIN_WPB = 4;  // wavefronts (tiles) per final-pass work-group
 constexpr int FIN_BLUR = 0, FIN_LAPLACIAN = 1, FIN_HESSIAN = 2;
 
