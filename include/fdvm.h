@@ -24,8 +24,12 @@
  *     right, y top to bottom (Appendix, Eqs A7-A8).
  *   - Device pointers are plain HIP device addresses; the caller owns every
  *     buffer (inputs, outputs, workspace).  The library allocates no device
- *     memory, keeps no pointer after returning and has no mutable global
- *     state; calls on different streams are independent.
+ *     memory and keeps no pointer after returning.  Its only state is that of
+ *     the batch call: per device, FDVM_MAX_LANES internal streams and events,
+ *     created on the first multi-lane batch call on that device (under a
+ *     lock) and kept until the process ends.  Calls on different streams are
+ *     independent, except that multi-lane batch calls that overlap on one
+ *     device share those streams and must be serialised by the caller.
  *   - Device work is enqueued on `stream` (a hipStream_t passed as void*;
  *     NULL = the legacy default stream) and the call returns without waiting.
  *     Argument errors are detected on the host before anything is enqueued;
@@ -390,6 +394,8 @@ size_t fdvm_batch_workspace_bytes(const fdvm_frame *frames, int nframes, int nsc
  *   outputs as fdvm_detect_blobs (count may exceed cap).
  *   The internal streams and events are created once per device and reused;
  *   calls that overlap on one device must not share them (serialise them).
+ *   Every lane forked from `stream` is joined back into it on every return
+ *   after the fork, also after a failed launch.
  * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM / FDVM_EUNSUPPORTED /
  * FDVM_EDEVICE as the single-frame calls; nothing is enqueued on a
  * validation error.

@@ -554,12 +554,24 @@ fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_
     if (ws_bytes < L.total() * (size_t)used) return FDVM_ENOMEM;
     hipStream_t origin = static_cast<hipStream_t>(stream);
     Lanes *lanes = nullptr;
+    int forked = 0;  // lanes that wait on the fork event and must be joined back
+    // every lane that was forked from `origin` is joined back into it, also
+    // after a failed launch, so that a capture of `origin` stays well formed
+    auto join = [&](fdvm_status status) -> fdvm_status {
+        for (int l = 0; l < forked; ++l) {
+            if (hipEventRecord(lanes->done[l], lanes->st[l]) != hipSuccess) status = FDVM_EDEVICE;
+            else if (hipStreamWaitEvent(origin, lanes->done[l], 0) != hipSuccess) status = FDVM_EDEVICE;
+        }
+        return status;
+    };
     if (used > 1) {
         lanes = lanes_for_current_device();
         if (!lanes) return FDVM_EDEVICE;
         if (hipEventRecord(lanes->fork, origin) != hipSuccess) return FDVM_EDEVICE;
-        for (int l = 0; l < used; ++l)
-            if (hipStreamWaitEvent(lanes->st[l], lanes->fork, 0) != hipSuccess) return FDVM_EDEVICE;
+        for (int l = 0; l < used; ++l) {
+            if (hipStreamWaitEvent(lanes->st[l], lanes->fork, 0) != hipSuccess) return join(FDVM_EDEVICE);
+            forked = l + 1;
+        }
     }
     for (int f = 0; f < nframes; ++f) {
         const fdvm_frame &fr = frames[f];
@@ -578,15 +590,9 @@ fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_
             e = launch_iir_cols(mid, W, mstride, rexp, V, H, W, W, H * W, true, prm, states, hs);
         if (e == hipSuccess)
             e = launch_detect(V, H, W, W, H * W, nscales, tau, border, fr.out, fr.cap, fr.count, det, hs);
-        if (e != hipSuccess) return FDVM_EDEVICE;
+        if (e != hipSuccess) return join(FDVM_EDEVICE);
     }
-    if (used > 1) {
-        for (int l = 0; l < used; ++l) {
-            if (hipEventRecord(lanes->done[l], lanes->st[l]) != hipSuccess) return FDVM_EDEVICE;
-            if (hipStreamWaitEvent(origin, lanes->done[l], 0) != hipSuccess) return FDVM_EDEVICE;
-        }
-    }
-    return FDVM_OK;
+    return join(FDVM_OK);
 }
 
 }  // extern "C"

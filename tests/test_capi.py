@@ -272,3 +272,16 @@ def test_butterworth_design_errors_and_unsupported_calls():
     assert L.fdvm_blur_iir_adjoint(a, 8, 8, 8, 64, b, 8, 64, one, 1, 0, ws, big, None) == P.EUNSUPPORTED
     with pytest.raises(P.FdvmError):
         P.iir_designs([2.0], P.BUTTERWORTH, dsigma=True)
+
+
+def test_batch_validates_every_frame_before_enqueueing():
+    # a bad descriptor after good ones: EINVAL on the host, nothing forked
+    L = P.lib()
+    frames = (P.Frame * 3)()
+    for f in frames:
+        f.data, f.dtype, f.H, f.W, f.row_chunk, f.pitch = 4096, P.U16, 64, 64, 0, 64
+        f.out, f.count, f.cap = 8192, 12288, 10
+    frames[2].pitch = 10   # pitch < W
+    filt = P.iir_designs([2.0, 4.0])
+    st = L.fdvm_batch_detect(frames, 3, filt, 2, P.BC_REPLICATE, 1.0, 1, 2, ctypes.c_void_p(4096), 1 << 40, None)
+    assert st == P.EINVAL
