@@ -24,12 +24,15 @@
  *     right, y top to bottom (Appendix, Eqs A7-A8).
  *   - Device pointers are plain HIP device addresses; the caller owns every
  *     buffer (inputs, outputs, workspace).  The library allocates no device
- *     memory and keeps no pointer after returning.  Its only state is that of
- *     the batch call: per device, FDVM_MAX_LANES internal streams and events,
- *     created on the first multi-lane batch call on that device (under a
- *     lock) and kept until the process ends.  Calls on different streams are
- *     independent, except that multi-lane batch calls that overlap on one
- *     device share those streams and must be serialised by the caller.
+ *     memory and keeps no pointer after returning.  Its only state: per
+ *     device, FDVM_MAX_LANES internal streams and events of the batch call
+ *     (created on the first multi-lane batch call on that device, under a
+ *     lock) and the fixed scratch array of the no-allocation calls (its
+ *     device address looked up on their first call there), both kept until
+ *     the process ends.  Calls on different streams are independent, except
+ *     that multi-lane batch calls that overlap on one device share those
+ *     streams, and no-allocation calls that overlap on one device share that
+ *     array: either must be serialised by the caller.
  *   - Device work is enqueued on `stream` (a hipStream_t passed as void*;
  *     NULL = the legacy default stream) and the call returns without waiting.
  *     Argument errors are detected on the host before anything is enqueued;
@@ -53,7 +56,7 @@ extern "C" {
 typedef enum {
     FDVM_OK = 0,
     FDVM_EINVAL = -1,       /* invalid argument (null pointer, bad size/pitch/enum) */
-    FDVM_ERANGE = -2,       /* sigma / length outside the supported design range */
+    FDVM_ERANGE = -2,       /* sigma / length / size outside the supported range */
     FDVM_ENOMEM = -3,       /* caller-provided buffer too small (taps, workspace) */
     FDVM_EDEVICE = -4,      /* a HIP call failed */
     FDVM_EOVERFLOW = -5,    /* more detections than the output capacity */
@@ -403,6 +406,37 @@ size_t fdvm_batch_workspace_bytes(const fdvm_frame *frames, int nframes, int nsc
 fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_filter *filters, int nscales,
                               fdvm_boundary bc, float tau, int border, int nlanes, void *ws, size_t ws_bytes,
                               void *stream);
+
+/* ------------------------------------------------------------------ no allocation
+ * For callers that cannot allocate device memory or pass a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  The library keeps one fixed scratch array of
+ * FDVM_NOALLOC_SCRATCH_BYTES in the memory of every device it runs on (from
+ * the first use on that device until the process ends); no call here
+ * allocates anything.
+ */
+#define FDVM_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* Size of the fixed scratch array of each device, in bytes. */
+size_t fdvm_noalloc_scratch_bytes(void);
+
+/*
+ * fdvm_detect_blobs_noalloc -- fdvm_detect_blobs (same arguments, same
+ *   results, same kernels) with its workspace taken from the device's fixed
+ *   scratch array instead of a caller buffer.  The caller still passes resp,
+ *   out_dev and count_dev.
+ * Returns FDVM_ERANGE when the call would need more than
+ *   FDVM_NOALLOC_SCRATCH_BYTES of workspace, i.e. when
+ *   fdvm_workspace_bytes(FDVM_OP_DETECT, H, W, nscales, 0) exceeds it (about
+ *   nscales * H * ceil(W / 62) * 8 bytes: 2048 x 2048 x 8 scales takes 4.5 MB,
+ *   4096 columns x 3072 rows x 12 scales 19.8 MB); otherwise as
+ *   fdvm_detect_blobs.  All calls on one device share its scratch array:
+ *   calls that overlap on one device (several streams or threads) race and
+ *   must be serialised by the caller.
+ */
+fdvm_status fdvm_detect_blobs_noalloc(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
+                                      int nscales, float tau, int border, fdvm_blob *out_dev, int32_t cap,
+                                      int32_t *count_dev, void *stream);
 
 #ifdef __cplusplus
 }

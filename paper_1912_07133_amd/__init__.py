@@ -115,6 +115,11 @@ def lib() -> ctypes.CDLL:
         L.fdvm_detect_blobs.restype = ctypes.c_int
         L.fdvm_detect_blobs.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_float,
                                         ctypes.c_int, vp, i32, vp, vp, ctypes.c_size_t, vp]
+        L.fdvm_noalloc_scratch_bytes.restype = ctypes.c_size_t
+        L.fdvm_noalloc_scratch_bytes.argtypes = []
+        L.fdvm_detect_blobs_noalloc.restype = ctypes.c_int
+        L.fdvm_detect_blobs_noalloc.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.c_float,
+                                                ctypes.c_int, vp, i32, vp, vp]
         L.fdvm_iir_hessian.restype = ctypes.c_int
         L.fdvm_iir_hessian.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, ctypes.POINTER(Filter),
                                        ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_int, vp,

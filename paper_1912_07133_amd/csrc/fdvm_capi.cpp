@@ -35,6 +35,19 @@ fdvm_status check_planes(const void *out, int64_t H, int64_t W, int64_t pitch, i
 
 }  // namespace
 
+namespace fdvm {
+fdvm_status detect_check(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, int nscales,
+                         float tau, int border, const void *out_dev, int32_t cap, const int32_t *count_dev) {
+    fdvm_status st = check_image(resp, H, W, pitch);
+    if (st != FDVM_OK) return st;
+    if (!out_dev || !count_dev) return FDVM_EINVAL;
+    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
+    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
+    if (!(tau >= 0.0f) || !std::isfinite(tau) || border < 0 || cap < 0) return FDVM_EINVAL;
+    return FDVM_OK;
+}
+}  // namespace fdvm
+
 extern "C" {
 
 const char *fdvm_status_string(fdvm_status s) {
@@ -446,12 +459,9 @@ fdvm_status fdvm_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch
 fdvm_status fdvm_detect_blobs(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                               int nscales, float tau, int border, fdvm_blob *out_dev, int32_t cap,
                               int32_t *count_dev, void *ws, size_t ws_bytes, void *stream) {
-    fdvm_status st = check_image(resp, H, W, pitch);
+    fdvm_status st = detect_check(resp, H, W, pitch, plane_stride, nscales, tau, border, out_dev, cap, count_dev);
     if (st != FDVM_OK) return st;
-    if (!out_dev || !count_dev || !ws) return FDVM_EINVAL;
-    if (nscales < 1 || nscales > FDVM_MAX_SCALES) return FDVM_EINVAL;
-    if (nscales > 1 && plane_stride < H * pitch) return FDVM_EINVAL;
-    if (!(tau >= 0.0f) || !std::isfinite(tau) || border < 0 || cap < 0) return FDVM_EINVAL;
+    if (!ws) return FDVM_EINVAL;
     if (ws_bytes < detect_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
     hipError_t e = launch_detect(resp, H, W, pitch, plane_stride, nscales, tau, border, out_dev, cap, count_dev,
                                  ws, static_cast<hipStream_t>(stream));

@@ -107,6 +107,9 @@ unsigned long long *detect_mask_words(void *ws);
 hipError_t launch_compact(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                           int nscales, const unsigned long long *pmask, fdvm_blob *out, int32_t cap,
                           int32_t *count, void *ws, hipStream_t stream);
+// host-side argument checks of fdvm_detect_blobs, workspace aside
+fdvm_status detect_check(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride, int nscales,
+                         float tau, int border, const void *out_dev, int32_t cap, const int32_t *count_dev);
 hipError_t launch_detect(const float *resp, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                          int nscales, float tau, int border, fdvm_blob *out, int32_t cap,
                          int32_t *count, void *ws, hipStream_t stream);

@@ -274,6 +274,22 @@ def test_butterworth_design_errors_and_unsupported_calls():
         P.iir_designs([2.0], P.BUTTERWORTH, dsigma=True)
 
 
+def test_noalloc_detect_rejects_sizes_beyond_its_scratch():
+    # host-side checks only: nothing reaches a device
+    L = P.lib()
+    cap_bytes = L.fdvm_noalloc_scratch_bytes()
+    assert cap_bytes == 32 << 20
+    fake = ctypes.c_void_p(4096)   # never dereferenced: the call fails validation first
+    H, W, S = 65535, 16384, 16
+    assert P.workspace_bytes(P.OP_DETECT, H, W, S) > cap_bytes
+    st = L.fdvm_detect_blobs_noalloc(fake, H, W, W, H * W, S, 0.1, 1, fake, 10, fake, None)
+    assert st == P.ERANGE
+    # the ordinary argument checks come first
+    assert L.fdvm_detect_blobs_noalloc(None, 10, 10, 10, 100, 1, 0.1, 1, fake, 10, fake, None) == P.EINVAL
+    assert L.fdvm_detect_blobs_noalloc(fake, 10, 10, 10, 100, 1, -1.0, 1, fake, 10, fake, None) == P.EINVAL
+    assert L.fdvm_detect_blobs_noalloc(fake, 10, 10, 10, 100, 0, 0.1, 1, fake, 10, fake, None) == P.EINVAL
+
+
 def test_batch_validates_every_frame_before_enqueueing():
     # a bad descriptor after good ones: EINVAL on the host, nothing forked
     L = P.lib()
