@@ -104,6 +104,37 @@ def fir_1d(x: np.ndarray, taps: np.ndarray, boundary: str = "replicate") -> np.n
     return y
 
 
+def fir_matrix(taps: np.ndarray, N: int, boundary: str = "replicate") -> np.ndarray:
+    """The N x N matrix of the FIR of Eq A5 on a length-N signal with its
+    extension folded in:  (T x)(n) = sum_{m=-K..K} h(m) x_ext(n - m), where
+    x_ext(j) = x(clamp(j)) ("replicate") or 0 outside [0, N) ("zero"), so
+    T[n, j] = sum of h(m) over the m with ext(n - m) = j."""
+    taps = np.asarray(taps, dtype=np.float64)
+    K = (len(taps) - 1) // 2
+    T = np.zeros((N, N))
+    n = np.arange(N)
+    for m in range(-K, K + 1):
+        j = n - m
+        if boundary == "replicate":
+            T[n, np.clip(j, 0, N - 1)] += taps[K + m]   # one entry per row n: no repeated index
+        elif boundary == "zero":
+            ok = (j >= 0) & (j < N)
+            T[n[ok], j[ok]] += taps[K + m]
+        else:
+            raise ValueError(boundary)
+    return T
+
+
+def blur_2d_matrix(image: np.ndarray, taps: np.ndarray, boundary: str = "replicate") -> np.ndarray:
+    """The separable FIR blur of blur_2d as two matrix products,
+    B = T_H X T_W^T (the x filter acts on the rows of X, the y filter on the
+    columns); the same linear map, summed in another order.  For full-size
+    frames, where the shifted sums of fir_1d take minutes."""
+    X = np.asarray(image, dtype=np.float64)
+    H, W = X.shape
+    return fir_matrix(taps, H, boundary) @ (X @ fir_matrix(taps, W, boundary).T)
+
+
 def apply_1d(x: np.ndarray, filt, boundary: str, axis: int) -> np.ndarray:
     """Apply an IIR (IIRCoefficients) or FIR (tap array) blur along `axis`."""
     xm = np.moveaxis(np.asarray(x, dtype=np.float64), axis, -1)

@@ -93,6 +93,20 @@ def test_separable_equals_brute_force_fir(boundary):
     assert np.max(np.abs(sep - bf)) < 1e-13
 
 
+@pytest.mark.parametrize("boundary", ["replicate", "zero"])
+@pytest.mark.parametrize("shape_hw,sigma,K", [((14, 18), 2.0, None), ((9, 31), 4.0, 20), ((23, 6), 1.5, 11)])
+def test_matrix_form_of_the_fir_equals_brute_force(boundary, shape_hw, sigma, K):
+    """Eq A5 as the matrix products T_H X T_W^T (extension folded into the
+    matrices), against the direct 2-D sum over the extended image, also with
+    taps longer than the frame (every tap folds onto an edge sample)."""
+    rng = np.random.default_rng(sum(shape_hw))
+    img = rng.random(shape_hw) * 7.0 - 2.0
+    taps = design.colored_sg_taps(sigma, K=K)
+    got = filtering.blur_2d_matrix(img, taps, boundary)
+    bf = filtering.brute_force_2d(img, taps, boundary)
+    assert np.max(np.abs(got - bf)) < 1e-13 * max(1.0, np.max(np.abs(bf)))
+
+
 def test_iir_equals_fir_with_its_impulse_response():
     """The DE with steady-state initialisation computes exactly the convolution
     of the replicate-extended signal with the infinite IR."""
