@@ -90,17 +90,38 @@ def blob_keys(blobs):
     return [(int(b["scale"]), int(b["y"]), int(b["x"]), int(b["polarity"])) for b in blobs]
 
 
-def compare_detections(got, ref, V_ref, V_got, tau):
-    """Returns (number of fragile decisions, mismatches outside the fragile
-    set).  Ordering of `got` must already be (scale, y, x)."""
-    errs = [float(np.max(np.abs(np.asarray(V_got[s], np.float64) - V_ref[s]))) for s in range(V_ref.shape[0])]
+def compare_detections(got, ref, V_ref, V_got, tau, border=1, v_bound=None):
+    """Compares a GPU detection list `got` (from the planes V_got) with the
+    oracle's list `ref` (from V_ref).  Returns (number of fragile decisions,
+    mismatches); the caller asserts that the mismatches are [].
+
+    * Outside the fragile set (decisions that an error of at most the measured
+      max |V_got - V_ref| of each plane could flip) the two lists must agree
+      exactly: (scale, y, x, polarity).
+    * Inside it neither list is held to the other's decisions, but the GPU list
+      must still be valid for its own planes: the whole GPU list must equal
+      the oracle's extremum rule applied to V_got (in float64, tau rounded to
+      float32 as the kernels compare it).  Entries that break this are
+      reported as ("invalid", s, y, x, polarity) or ("missing", ...).
+    * v_bound (optional, per plane): an a-priori bound on |V_got - V_ref|.  The
+      measured errors size the fragile set, so they must not exceed it
+      (reported as ("bound", s, error, bound)).
+    Ordering of `got` must already be (scale, y, x)."""
+    S = V_ref.shape[0]
+    errs = [float(np.max(np.abs(np.asarray(V_got[s], np.float64) - V_ref[s]))) for s in range(S)]
     frag = fragile_mask(V_ref, errs, tau)
     g = set(blob_keys(got))
     r = set(blob_keys(ref))
     keep = lambda k: not frag[k[0], k[1], k[2]]  # noqa: E731
     g2 = {k for k in g if keep(k)}
     r2 = {k for k in r if keep(k)}
-    return int(frag.sum()), sorted(g2 ^ r2)
+    mism = sorted(g2 ^ r2)
+    from oracle import shape
+    own = set(blob_keys(shape.detect_extrema(np.asarray(V_got, np.float64), float(np.float32(tau)), border)))
+    mism += [("invalid",) + k for k in sorted(g - own)] + [("missing",) + k for k in sorted(own - g)]
+    if v_bound is not None:
+        mism += [("bound", s, errs[s], float(v_bound[s])) for s in range(S) if not errs[s] <= v_bound[s]]
+    return int(frag.sum()), mism
 
 
 def torch_cuda():

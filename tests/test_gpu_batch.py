@@ -5,7 +5,8 @@
 * Lane counts 1 .. 8 give identical results.
 * Row-pass chunk overrides change only the float64 rounding of the recursion
   (positions, scales and polarities equal; values within 1e-5 relative).
-* One frame against the FP64 oracle (fragile-decision rule of parity.py).
+* Frames against the FP64 oracle (fragile-decision rule of parity.py): one
+  small frame, and one frame of every size of the 64-frame workload.
 * The batch captured into a graph and replayed several times, with eager work
   between the replays, reproduces the eager results each time."""
 
@@ -14,7 +15,7 @@ import pytest
 
 import synthetic as syn
 from oracle import design, filtering, shape
-from parity import compare_detections, say
+from parity import compare_detections, laplacian_tolerance, say
 
 pytestmark = pytest.mark.gpu
 
@@ -109,6 +110,43 @@ def test_batch_frame_against_oracle():
     say(f"   detections gpu={len(got[0])} ref={len(det_ref)} fragile={nfrag}")
     assert mism == []
     assert len(det_ref) > 0
+
+
+def _oracle_check(frame_u16, sig, det_gpu, V_gpu, tau, what):
+    a = frame_u16.astype(np.float64)
+    B = filtering.blur_bank(a, [design.repeated_pole(3, s) for s in sig])
+    V_ref = shape.laplacian_bank(B, sig)
+    det_ref = shape.detect_extrema(V_ref, tau, 1)
+    vb = [laplacian_tolerance(sg, B[s]) for s, sg in enumerate(sig)]
+    nfrag, mism = compare_detections(det_gpu, det_ref, V_ref, V_gpu, tau, 1, v_bound=vb)
+    say(f"   {what}: detections gpu={len(det_gpu)} ref={len(det_ref)} fragile={nfrag}")
+    assert mism == [], what
+    assert len(det_ref) > 0
+    assert nfrag <= 0.001 * V_gpu.size, what
+
+
+def test_batch_workload_sizes_against_oracle():
+    """One frame of every size of the 64-frame workload (512 x 512,
+    1080 x 1920, 2048 x 2048 with its 12 scales; 3072 x 4096 with 4 of them),
+    through the batch call, against the FP64 oracle."""
+    cfg = syn.BATCH
+    specs = {}
+    for (H, W, seed) in syn.batch_frames():
+        specs.setdefault((H, W), seed)
+    small = [(512, 512), (1080, 1920), (2048, 2048)]
+    runs = [(small, cfg["sigmas"]), ([(3072, 4096)], [cfg["sigmas"][i] for i in (0, 4, 8, 11)])]
+    for sizes, sig in runs:
+        arrays = [syn.aerial_frame(H, W, specs[(H, W)], nblobs=int(round(200 * H * W / 2048 ** 2)))
+                  for (H, W) in sizes]
+        frames = [torch.from_numpy(a.view(np.int16)).cuda() for a in arrays]
+        say(f"case: batch workload sizes {sizes}, {len(sig)} scales")
+        b = P.Batch(frames, sig, cfg["tau"], nlanes=2)
+        b.run()
+        got = b.results()
+        for a, f, g, (H, W) in zip(arrays, frames, got, sizes):
+            V_gpu = P.iir_laplacian(f, sig).cpu().numpy()
+            _oracle_check(a, sig, g, V_gpu, cfg["tau"], f"{H}x{W}")
+            del V_gpu
 
 
 def test_batch_graph_replays():

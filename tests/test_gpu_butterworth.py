@@ -85,7 +85,8 @@ def test_fused_laplacian_and_detection():
         err = float(np.max(np.abs(Vn[s] - V_ref[s])))
         assert err <= laplacian_tolerance(sg, B_ref[s]), (s, err)
     det = P.detect_blobs(V, tau, 1)
-    nfrag, mism = compare_detections(det, det_ref, V_ref, Vn, tau)
+    vb = [laplacian_tolerance(sg, B_ref[s]) for s, sg in enumerate(sigmas)]
+    nfrag, mism = compare_detections(det, det_ref, V_ref, Vn, tau, 1, v_bound=vb)
     say(f"   detections gpu={len(det)} ref={len(det_ref)} fragile={nfrag}")
     assert mism == []
     assert len(det_ref) > 10

@@ -12,7 +12,7 @@ import pytest
 
 import synthetic as syn
 from oracle import design, filtering, shape
-from parity import RTOL_BLUR, assert_planes_close, compare_detections, keys_equal_ok, say
+from parity import RTOL_BLUR, assert_planes_close, compare_detections, keys_equal_ok, laplacian_tolerance, say
 
 pytestmark = pytest.mark.gpu
 
@@ -41,6 +41,8 @@ def test_tiny_config_end_to_end():
     say(f"   detections gpu={len(det)} ref={len(det_ref)} fragile={nfrag}")
     assert mism == []
     assert len(det_ref) > 0
+    # the tiny configuration: blob positions and scales exactly the oracle's
+    assert keys_equal_ok(det, det_ref)
 
 
 def test_tiny_noise_free_exact():
@@ -61,7 +63,9 @@ def test_tiny_seeds_multi_scale(seed):
     _, V_ref, det_ref = run_oracle(img.astype(np.float64), sig, 3, 0.3)
     det, V = P.detect(torch.from_numpy(img).cuda(), sig, 0.3, order=3)
     nfrag, mism = compare_detections(det, det_ref, V_ref, V.cpu().numpy(), 0.3)
+    say(f"   detections gpu={len(det)} ref={len(det_ref)} fragile={nfrag}")
     assert mism == []
+    assert keys_equal_ok(det, det_ref)
 
 
 # Bounds per route on the 2048 x 2048 frame (8 scales, sigma up to 64):
@@ -97,7 +101,8 @@ def test_full_frame_end_to_end():
         det = P.detect_blobs(V, cfg["tau"], cfg["border"])
         Vn = V.cpu().numpy()
         dv = max(float(np.max(np.abs(Vn[s] - V_ref[s]))) for s in range(len(cfg["sigmas"])))
-        nfrag, mism = compare_detections(det, det_ref, V_ref, Vn, cfg["tau"])
+        vb = [laplacian_tolerance(sg, B_ref[s]) for s, sg in enumerate(cfg["sigmas"])]
+        nfrag, mism = compare_detections(det, det_ref, V_ref, Vn, cfg["tau"], cfg["border"], v_bound=vb)
         stats[name] = (nfrag / Vn.size, abs(len(det) - len(det_ref)) / len(det_ref), mism)
         say(f"   {name}: detections gpu={len(det)} ref={len(det_ref)} fragile={nfrag} max|dV|={dv:.3g}")
     for name, (ffrac, dcount, mism) in stats.items():
