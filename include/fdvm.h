@@ -257,6 +257,33 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
                           void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * fdvm_fir_laplacian -- the FIR form of the detection response:
+ *   V_s = sigma_s^2 (D20 + D02) B_s with B_s the separable FIR blur of Eq A5
+ *   (x then y, extension bc) and the Table I d = 2 differences taken on the
+ *   replicate extension of B_s (as fdvm_highpass), in one call.  Both FIR
+ *   passes accumulate in float64 and the x-pass planes are float64, so the
+ *   blur is never rounded before the second differences (the normalised
+ *   Laplacian multiplies a rounding of B by about 8 sigma^2); only V is
+ *   rounded, to float32.  This is the FIR counterpart of fdvm_iir_laplacian,
+ *   the input of fdvm_detect_blobs (Section 5, the low-pass then high-pass
+ *   stages of the two-stage filter bank).
+ *   Image arguments and out as fdvm_iir_laplacian.
+ *   taps_dev  DEVICE float64 array: the taps of scale s are taps_dev[tap_offset[s]
+ *             .. tap_offset[s] + 2 K_s] = h(-K_s) .. h(K_s) (as written by
+ *             fdvm_filter_design); read by the kernels, not modified.
+ *   half_len, tap_offset  host int32[nscales]; K_s in [1, FDVM_MAX_FIR_HALF].
+ *   sigmas    host float64[nscales], > 0: the normalisation sigma_s^2.
+ *   ws, ws_bytes device workspace of at least
+ *             fdvm_workspace_bytes(FDVM_OP_FIR_LAPLACIAN, H, W, nscales, 0)
+ *             bytes (one float64 x-pass plane, reused scale by scale).
+ * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM / FDVM_EDEVICE.
+ */
+fdvm_status fdvm_fir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                               int64_t out_pitch, int64_t plane_stride, const double *taps_dev,
+                               const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                               int nscales, fdvm_boundary bc, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * fdvm_iir_hessian -- the paper's blob detector (Section 5, Eqs 26-27) on the
  * IIR blur (repeated-pole or Butterworth designs), fused like
  * fdvm_iir_laplacian: per scale and pixel the
@@ -320,7 +347,8 @@ fdvm_status fdvm_plane_dots(const float *a, const float *b, int64_t H, int64_t W
 
 /* workspace sizes */
 enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3,
-       FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5, FDVM_OP_IIR_HESSIAN = 6 };
+       FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5, FDVM_OP_IIR_HESSIAN = 6,
+       FDVM_OP_FIR_LAPLACIAN = 7 };
 
 /* Bytes of device workspace `op` needs for an H x W frame with nscales
  * scales and maximum FIR half-length max_half_len (0 if unused). */

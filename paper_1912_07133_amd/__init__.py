@@ -33,7 +33,8 @@ BC_REPLICATE, BC_ZERO = 0, 1
 U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
-OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN = range(7)
+(OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN,
+ OP_FIR_LAPLACIAN) = range(8)
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
 
@@ -109,6 +110,10 @@ def lib() -> ctypes.CDLL:
         L.fdvm_blur_fir.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64,
                                     ctypes.POINTER(dbl), ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
+        L.fdvm_fir_laplacian.restype = ctypes.c_int
+        L.fdvm_fir_laplacian.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, vp, ctypes.POINTER(i32),
+                                         ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int, ctypes.c_int, vp,
+                                         ctypes.c_size_t, vp]
         L.fdvm_highpass.restype = ctypes.c_int
         L.fdvm_highpass.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.POINTER(dbl),
                                     ctypes.c_uint, ctypes.c_int, vp, i64, vp]
@@ -353,6 +358,46 @@ def blur_fir(x, sigmas: Sequence[float], kind: str = "sg", half_lens: Sequence[i
     return out
 
 
+def fir_taps_device(kind: str, sigmas: Sequence[float], half_lens: Sequence[int] | None, device):
+    """(taps on `device` as float64, half_len, offsets) for fdvm_fir_laplacian;
+    designs are pure functions of their arguments, so the device copies are
+    memoised per device (callers must not modify them)."""
+    key = (kind, tuple(float(s) for s in sigmas), None if half_lens is None else tuple(int(k) for k in half_lens),
+           str(device))
+    hit = _DEVICE_TAPS.get(key)
+    if hit is None:
+        torch = _torch()
+        t, half, off = fir_taps(kind, sigmas, half_lens)
+        hit = (torch.from_numpy(np.ascontiguousarray(t, dtype=np.float64)).to(device),
+               np.ascontiguousarray(half, dtype=np.int32), np.ascontiguousarray(off, dtype=np.int32))
+        _DEVICE_TAPS[key] = hit
+    return hit
+
+
+_DEVICE_TAPS: dict = {}
+
+
+def fir_laplacian(x, sigmas: Sequence[float], kind: str = "sg", half_lens: Sequence[int] | None = None,
+                  boundary: str = "replicate", out=None, workspace=None):
+    """FIR blur + normalised Laplacian in one call (fdvm_fir_laplacian):
+    [H, W] -> float32 V [S, H, W]."""
+    torch = _torch()
+    x = _frame(x)
+    H, W = x.shape
+    S = len(sigmas)
+    taps, half, off = fir_taps_device(kind, sigmas, half_lens, x.device)
+    if out is None:
+        out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
+    ws = _workspace(OP_FIR_LAPLACIAN, H, W, S, x.device, workspace)
+    ip = ctypes.POINTER(ctypes.c_int32)
+    sig = (ctypes.c_double * S)(*[float(s) for s in sigmas])
+    _check(lib().fdvm_fir_laplacian(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(), out.stride(1),
+                                    out.stride(0), taps.data_ptr(), half.ctypes.data_as(ip), off.ctypes.data_as(ip),
+                                    sig, S, BOUNDARIES[boundary], ws.data_ptr(), ws.numel(), _stream_ptr(x.device)),
+           "fdvm_fir_laplacian")
+    return out
+
+
 def highpass(blur, sigmas: Sequence[float], what: int = HP_LAPLACIAN, normalize: bool = True, out=None):
     """fdvm_highpass on float32 planes [S, H, W] -> [S, nout, H, W] (nout =
     number of bits in `what`; squeezed to [S, H, W] when nout == 1)."""
@@ -401,14 +446,13 @@ def detect_blobs(resp, tau: float, border: int = 1, cap: int = 1 << 20, workspac
 
 
 def detect(frame, sigmas: Sequence[float], tau: float, kind: str = "iir", order: int = 3,
-           boundary: str = "replicate", border: int = 1, cap: int = 1 << 20, algo: int = FIR_DIRECT):
-    """The whole filter bank: blur (IIR or FIR) -> normalised Laplacian ->
-    multi-scale extrema.  Returns (blob list, Laplacian planes)."""
+           boundary: str = "replicate", border: int = 1, cap: int = 1 << 20):
+    """The whole filter bank: blur (IIR or FIR) fused with the normalised
+    Laplacian -> multi-scale extrema.  Returns (blob list, Laplacian planes)."""
     if kind == "iir":
         V = iir_laplacian(frame, sigmas, order=order, boundary=boundary)
     else:
-        B = blur_fir(frame, sigmas, kind=kind, boundary=boundary, algo=algo)
-        V = highpass(B, sigmas, HP_LAPLACIAN, True)
+        V = fir_laplacian(frame, sigmas, kind=kind, boundary=boundary)
     return detect_blobs(V, tau, border, cap), V
 
 

@@ -152,6 +152,7 @@ size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_h
             return (((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255) +
                    iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS) + fold_workspace_bytes(H, W, nscales);
         case FDVM_OP_PLANE_DOTS: return dots_workspace_bytes(H, nscales);
+        case FDVM_OP_FIR_LAPLACIAN: return fir_laplacian_workspace_bytes(H, W);
         case FDVM_OP_IIR_HESSIAN:
             return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
                    iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H) +
@@ -432,6 +433,27 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     hipError_t e = launch_fir(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, taps, half_len, tap_offset,
                               nscales, bc, algo, ws, ws_bytes, static_cast<hipStream_t>(stream));
     return from_hip(e);
+}
+
+fdvm_status fdvm_fir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                               int64_t out_pitch, int64_t plane_stride, const double *taps_dev,
+                               const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                               int nscales, fdvm_boundary bc, void *ws, size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
+    if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
+    if (!taps_dev || !half_len || !tap_offset || !sigmas || !ws) return FDVM_EINVAL;
+    for (int s = 0; s < nscales; ++s) {
+        if (half_len[s] < 1 || half_len[s] > FDVM_MAX_FIR_HALF) return FDVM_ERANGE;
+        if (tap_offset[s] < 0) return FDVM_EINVAL;
+        if (!finite_pos(sigmas[s])) return FDVM_ERANGE;
+    }
+    if (ws_bytes < fir_laplacian_workspace_bytes(H, W)) return FDVM_ENOMEM;
+    return from_hip(launch_fir_laplacian(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, taps_dev, half_len,
+                                         tap_offset, sigmas, nscales, bc, ws, static_cast<hipStream_t>(stream)));
 }
 
 fdvm_status fdvm_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,

@@ -131,6 +131,14 @@ size_t dots_workspace_bytes(int64_t H, int nscales);
 hipError_t launch_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch, int64_t plane,
                              int nscales, double *out, void *ws, hipStream_t st);
 
+// FIR blur fused with the normalised Laplacian (float64 accumulation and
+// x-pass plane; ws: fir_laplacian_workspace_bytes)
+size_t fir_laplacian_workspace_bytes(int64_t H, int64_t W);
+hipError_t launch_fir_laplacian(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                                int64_t out_pitch, int64_t plane_stride, const double *taps_dev,
+                                const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                                int nscales, int boundary, void *ws, hipStream_t stream);
+
 bool fir_mfma_available();
 // Toeplitz-block FIR on the matrix cores: y pass of `in` into tmp (nscales
 // transposed W x H planes), x pass of tmp transposed back into `out`.
