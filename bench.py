@@ -233,7 +233,8 @@ def run_grad_leg(P, syn, torch, np, dev, stream, log):
 def run_precision_leg(P, syn, torch, np, dev, stream, log):
     """One 8192 x 8192 frame (generator seed 3, 3200 blobs, / 4095) stored as
     float16 and as bfloat16; coloured SG FIR of lengths 33, 65, 129, 257
-    (sigma = K / 3, direct and Toeplitz/MFMA) and the K = 3 IIR at the same
+    (sigma = K / 3: direct, Toeplitz on the matrix cores with float32 operands
+    and with the frame's half type as operands) and the K = 3 IIR at the same
     sigmas.  Throughput per form; the outputs at 16 sampled pixels are kept
     for the error figures, which the CPU-baseline leg computes against FP64
     references (precision_errors)."""
@@ -247,11 +248,22 @@ def run_precision_leg(P, syn, torch, np, dev, stream, log):
     out = {"workload": cfg["name"], "scales": [round(s, 4) for s in sig], "fir_lengths": cfg["fir_lengths"],
            "error": "max |gpu - fp64| / max |fp64| over 16 sampled pixels, per scale", "forms": {},
            "_pts": pts, "_sig": sig, "_Ks": Ks, "_samples": {}}
+    # designs, output planes and workspaces made once, outside the timed calls
+    tp = P.fir_taps("sg", sig, Ks)
+    outB = torch.empty((len(sig), cfg["H"], cfg["W"]), dtype=torch.float32, device=dev)
+    ws_f = torch.empty(P.workspace_bytes(P.OP_BLUR_FIR, cfg["H"], cfg["W"], len(sig), max(Ks)), dtype=torch.uint8,
+                       device=dev)
+    ws_i = torch.empty(P.workspace_bytes(P.OP_BLUR_IIR, cfg["H"], cfg["W"], len(sig)), dtype=torch.uint8, device=dev)
     for kind, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
         x = torch.from_numpy(orig.astype(np.float32)).to(tdt).to(dev)
-        runs = {"iir": lambda: P.blur_iir(x, sig, order=3),
-                "fir_direct": lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=P.FIR_DIRECT),
-                "fir_mfma": lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=P.FIR_TOEPLITZ_MFMA)}
+
+        def fir_form(algo):
+            return lambda: P.blur_fir(x, sig, kind="sg", half_lens=Ks, algo=algo, out=outB, workspace=ws_f, taps=tp)
+
+        runs = {"iir": lambda: P.blur_iir(x, sig, order=3, out=outB, workspace=ws_i),
+                "fir_direct": fir_form(P.FIR_DIRECT),
+                "fir_mfma": fir_form(P.FIR_TOEPLITZ_MFMA),
+                "fir_mfma_half": fir_form(P.FIR_TOEPLITZ_MFMA_HALF)}
         for name, fn in runs.items():
             B = fn()
             torch.cuda.synchronize()
@@ -262,13 +274,37 @@ def run_precision_leg(P, syn, torch, np, dev, stream, log):
             e1.record(stream)
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / 3
-            Bn = B.cpu().numpy()
-            out["_samples"][f"{kind}_{name}"] = [[float(Bn[s, i, j]) for i, j in pts] for s in range(len(sig))]
+            idx = torch.tensor([i * cfg["W"] + j for i, j in pts], device=dev)
+            Bn = B.reshape(len(sig), -1)[:, idx].cpu().numpy()
+            out["_samples"][f"{kind}_{name}"] = [[float(v) for v in Bn[s]] for s in range(len(sig))]
             out["forms"][f"{kind}_{name}"] = {"ms": round(ms, 3), "value": round(mpx / (ms / 1e3), 1)}
+            if name == "fir_mfma_half":
+                fl = half_mfma_flops(cfg["H"], cfg["W"], Ks)
+                out["forms"][f"{kind}_{name}"]["mfma_issued_tflops"] = round(fl / (ms / 1e3) / 1e12, 1)
+                out["forms"][f"{kind}_{name}"]["mfma_frac_of_dense_peak"] = round(fl / (ms / 1e3) / 2.5e15, 4)
             del B
         log(f"precision {kind}: " + ", ".join(f"{k.split('_', 1)[1]} {v['ms']:.2f} ms"
                                             for k, v in out["forms"].items() if k.startswith(kind)))
+    del outB, ws_f, ws_i
     return out
+
+
+def half_mfma_flops(H, W, Ks, first_pass_products=2):
+    """Matrix-core flops the half-operand Toeplitz FIR issues for one H x W
+    frame: per pass and scale, one wavefront per 32 rows x 64 outputs along
+    the rows runs 2 K'/16 + 4 groups of 16 samples (K' = K rounded up to 16),
+    each meeting one 32 x 32 output block in the first and last two groups and
+    both otherwise, with 2 products per block in the first pass (hi and lo
+    taps; 3 for uint16 frames, whose samples are split too) and 3 in the
+    second (the split intermediate); 32 * 32 * 16 * 2 flops each."""
+    total = 0
+    for K in Ks:
+        kp = -(-K // 16) * 16
+        blocks = 2 * (2 * kp // 16 + 4) - 4
+        for (rows, n), prods in (((H, W), first_pass_products), ((W, H), 3)):
+            waves = -(-rows // 32) * -(-n // 64)
+            total += waves * blocks * prods * 32 * 32 * 16 * 2
+    return total
 
 
 def precision_errors(prec, syn, torch, np, log):
@@ -293,7 +329,7 @@ def precision_errors(prec, syn, torch, np, log):
                     for s in sig]}
     for kind, tdt in (("f16", torch.float16), ("bf16", torch.bfloat16)):
         deq = torch.from_numpy(orig.astype(np.float32)).to(tdt).float().numpy().astype(np.float64)
-        for name in ("iir", "fir_direct", "fir_mfma"):
+        for name in ("iir", "fir_direct", "fir_mfma", "fir_mfma_half"):
             key = f"{kind}_{name}"
             if key not in prec["_samples"]:
                 continue
@@ -511,12 +547,19 @@ def main() -> int:
         log(f"FIR fused: {fms:.4f} ms/step, {fir['fused']['value']:.0f} Mpx*scales/s "
             f"(fir_laplacian {fper[0]:.3f} ms), detections {n_fir}")
         fir["blur_only"] = {}
-        for name, algo in (("direct", P.FIR_DIRECT), ("mfma", P.FIR_TOEPLITZ_MFMA)):
+        arith = {"direct": "float32", "mfma": "float32 operands and accumulation",
+                 "mfma_half": "float16 operand pairs (exact split of the uint16 samples), float32 accumulation"}
+        for name, algo in (("direct", P.FIR_DIRECT), ("mfma", P.FIR_TOEPLITZ_MFMA),
+                           ("mfma_half", P.FIR_TOEPLITZ_MFMA_HALF)):
             btot, _, bper = timed(fir_blur_for(algo), 2, fsteps, max(1, args.warmup // 5))
             fir["blur_only"][name] = {"blur_ms": round(bper[0], 4),
                                       "value": round(mpx / (bper[0] / 1e3), 1),
                                       "useful_TFLOPs": round(useful / (bper[0] / 1e3) / 1e12, 2),
-                                      "arith": "float32"}
+                                      "arith": arith[name]}
+            if name == "mfma_half":
+                fl = half_mfma_flops(H, W, [int(k) for k in half], first_pass_products=3)
+                fir["blur_only"][name]["mfma_issued_tflops"] = round(fl / (bper[0] / 1e3) / 1e12, 1)
+                fir["blur_only"][name]["mfma_frac_of_dense_peak"] = round(fl / (bper[0] / 1e3) / 2.5e15, 4)
             log(f"FIR blur {name}: {bper[0]:.3f} ms ({fir['blur_only'][name]['useful_TFLOPs']} useful TFLOP/s)")
         # per scale: the IIR and the FIR detection responses of one scale per call
         filt_all = designs()

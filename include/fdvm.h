@@ -77,7 +77,7 @@ typedef enum { FDVM_BC_REPLICATE = 0, FDVM_BC_ZERO = 1 } fdvm_boundary;
 
 typedef enum { FDVM_U16 = 0, FDVM_F32 = 1, FDVM_F16 = 2, FDVM_BF16 = 3 } fdvm_dtype;
 
-typedef enum { FDVM_FIR_DIRECT = 0, FDVM_FIR_TOEPLITZ_MFMA = 1 } fdvm_fir_algo;
+typedef enum { FDVM_FIR_DIRECT = 0, FDVM_FIR_TOEPLITZ_MFMA = 1, FDVM_FIR_TOEPLITZ_MFMA_HALF = 2 } fdvm_fir_algo;
 
 /* high-pass outputs (bit mask for fdvm_highpass `what`) */
 enum {
@@ -239,14 +239,22 @@ fdvm_status fdvm_iir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
  *   half_len  host int32[nscales], each in [1, FDVM_MAX_FIR_HALF].
  *   tap_offset host int32[nscales].
  *   algo      FDVM_FIR_DIRECT (LDS-staged direct convolution, float32, x then
- *             y) or FDVM_FIR_TOEPLITZ_MFMA (Toeplitz-block products on the
+ *             y), FDVM_FIR_TOEPLITZ_MFMA (Toeplitz-block products on the
  *             matrix cores, float32 operands and accumulation, y then x: the
  *             two orders agree up to rounding for a separable filter with a
- *             separable extension, Section 2).
+ *             separable extension, Section 2) or FDVM_FIR_TOEPLITZ_MFMA_HALF
+ *             (the same products with half-precision operands, float32
+ *             accumulation, x then y: float16 and bfloat16 frames are the
+ *             operands as stored, uint16 frames are split exactly into a
+ *             float16 pair; the taps and the intermediate are each carried
+ *             as a hi + lo pair of the operand type, so the dc gain and
+ *             moments of the taps hold to ~2^-22 (float16 operands) /
+ *             ~2^-16 (bfloat16); dt FDVM_F32 gives FDVM_EINVAL).
  *   ws, ws_bytes device workspace of at least
  *             fdvm_workspace_bytes(FDVM_OP_BLUR_FIR, H, W, nscales, maxK) bytes
  *             (the first-pass planes: one for FDVM_FIR_DIRECT, nscales
- *             transposed ones for FDVM_FIR_TOEPLITZ_MFMA).
+ *             transposed ones for the Toeplitz forms, plus the half form's
+ *             tap tables).
  * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM (workspace too small) /
  * FDVM_EDEVICE.
  */

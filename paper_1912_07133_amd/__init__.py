@@ -31,7 +31,7 @@ IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN, IIR_REPEATED_POLE_DSIGMA, IIR_B
 BUTTERWORTH = "butterworth"
 BC_REPLICATE, BC_ZERO = 0, 1
 U16, F32, F16, BF16 = 0, 1, 2, 3
-FIR_DIRECT, FIR_TOEPLITZ_MFMA = 0, 1
+FIR_DIRECT, FIR_TOEPLITZ_MFMA, FIR_TOEPLITZ_MFMA_HALF = 0, 1, 2
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
 (OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN,
  OP_FIR_LAPLACIAN) = range(8)

@@ -415,7 +415,9 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
     if (!taps || !half_len || !tap_offset || !ws) return FDVM_EINVAL;
     if (dt != FDVM_U16 && dt != FDVM_F32 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
     if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
-    if (algo != FDVM_FIR_DIRECT && algo != FDVM_FIR_TOEPLITZ_MFMA) return FDVM_EINVAL;
+    if (algo != FDVM_FIR_DIRECT && algo != FDVM_FIR_TOEPLITZ_MFMA && algo != FDVM_FIR_TOEPLITZ_MFMA_HALF)
+        return FDVM_EINVAL;
+    if (algo == FDVM_FIR_TOEPLITZ_MFMA_HALF && dt == FDVM_F32) return FDVM_EINVAL;
     int maxK = 0;
     for (int s = 0; s < nscales; ++s) {
         if (half_len[s] < 1 || half_len[s] > FDVM_MAX_FIR_HALF) return FDVM_ERANGE;
@@ -427,9 +429,7 @@ fdvm_status fdvm_blur_fir(const void *in, fdvm_dtype dt, int64_t H, int64_t W, i
             if (h[K + m] != h[K - m]) return FDVM_EINVAL;  // symmetric taps only
     }
     if (ws_bytes < fir_workspace_bytes(H, W, nscales, maxK)) return FDVM_ENOMEM;
-    if (algo == FDVM_FIR_TOEPLITZ_MFMA) {
-        if (!fir_mfma_available()) return FDVM_EUNSUPPORTED;
-    }
+    if (algo != FDVM_FIR_DIRECT && !fir_mfma_available()) return FDVM_EUNSUPPORTED;
     hipError_t e = launch_fir(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, taps, half_len, tap_offset,
                               nscales, bc, algo, ws, ws_bytes, static_cast<hipStream_t>(stream));
     return from_hip(e);

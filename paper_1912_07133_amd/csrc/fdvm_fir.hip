@@ -188,10 +188,14 @@ hipError_t rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, float 
 
 size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half) {
     (void)max_half;
-    // direct: one row-pass plane; Toeplitz/MFMA: one transposed plane per scale
+    // direct: one row-pass plane; Toeplitz/MFMA: one transposed plane per
+    // scale (float32 operands) or tap tables and a transposed pair of half
+    // planes per scale (half operands)
     const size_t direct = ((size_t)H * (size_t)W * sizeof(float) + 255) & ~(size_t)255;
     const size_t mfma = fir_mfma_workspace_bytes(H, W, nscales);
-    return direct > mfma ? direct : mfma;
+    const size_t half = fir_mfma_half_workspace_bytes(H, W, nscales);
+    const size_t m = direct > mfma ? direct : mfma;
+    return m > half ? m : half;
 }
 
 hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, float *out,
@@ -204,6 +208,9 @@ hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t i
     if (algo == FDVM_FIR_TOEPLITZ_MFMA)
         return launch_fir_mfma(in, dtype, H, W, in_pitch, tmp, out, out_pitch, plane_stride, taps, half_len,
                                tap_offset, nscales, boundary, st);
+    if (algo == FDVM_FIR_TOEPLITZ_MFMA_HALF)
+        return launch_fir_mfma_half(in, dtype, H, W, in_pitch, ws, out, out_pitch, plane_stride, taps, half_len,
+                                    tap_offset, nscales, boundary, st);
     for (int s = 0; s < nscales; ++s) {
         float *dst = out + (int64_t)s * plane_stride;
         Half hh;

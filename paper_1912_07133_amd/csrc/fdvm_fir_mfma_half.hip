@@ -1,0 +1,495 @@
+// Toeplitz-block FIR (Eq A5) on the gfx950 matrix cores with half-precision
+// operands and float32 accumulation (v_mfma_f32_32x32x16_f16 / _bf16), for
+// frames stored as float16 or bfloat16 (the operands are the stored samples,
+// exactly) and as uint16 (each sample split exactly into a float16 pair).
+//
+// Precision.  Each tap h (scaled per scale by a power of two 2^e that brings
+// the largest to [0.5, 1)) is carried as a pair of the operand type: hi = h
+// rounded, lo' = (h - hi) 2^L rounded (L = 11 for float16, 8 for bfloat16),
+// so the taps keep 22 / 16 significant bits and the unit dc gain and the
+// vanishing moments of the design (Eqs 7, 11) hold to about 2^-22 / 2^-16.
+// The intermediate between the passes is stored as the same kind of pair.
+// Products of hi parts go to one accumulator, products with one lo' part to a
+// second, and the result is main + 2^-L second: scaling lo' by 2^L keeps it a
+// normal number of the half type (no bits lost to subnormals), and the
+// dropped lo' x lo' product is 2^-2L of the terms.  float16 intermediates are
+// stored times 2^-4 so that sums of samples up to 65504 stay finite.
+//
+// Geometry.  One kernel filters the rows of a plane along their length and
+// writes the result transposed; run twice (frame -> transposed pair planes ->
+// output planes) it is the separable blur.  Per wavefront 32 rows y0 + i and
+// 64 outputs p0 .. p0 + 63 along the rows, as two 32 x 32 blocks t = 0, 1.
+// One instruction takes 16 consecutive samples of each row:
+//     D_t[i][j] += sum_{k=0..15} x(y0 + i, r + k) h(p0 + 32 t + j - r - k)
+// A (32 x 16): lane i + 32 g holds samples r + 8 g .. r + 8 g + 7 of row
+// y0 + i, one 16-byte load; B (16 x 32): lane j + 32 g holds h(c - 8 g - u),
+// u = 0..7, c = p0 + 32 t + j - r, one 16-byte LDS read from a table whose
+// entry c is h(c), h(c - 1), .., h(c - 7) (hi, and lo').  With the half-
+// length rounded up to K' (a multiple of 32), groups g = 0 .. 2K'/16 + 3 of
+// 16 samples from p0 - K' meet block 0 for g <= 2K'/16 + 1 and block 1 for
+// g >= 2, and block 1 at group g + 2 uses block 0's B fragment of group g,
+// so each group reads one fragment pair from LDS.  The tables are built once
+// per call in the workspace and copied to LDS by every work-group.
+#include <cmath>
+#include <type_traits>
+
+#include "fdvm_internal.h"
+
+namespace fdvm {
+namespace {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int HT_ROWS = 32;       // rows per wavefront
+constexpr int HT_POS = 64;        // outputs per wavefront along the rows (two blocks)
+constexpr int HT_WPB = 4;         // wavefronts per work-group
+// two wavefronts stacked across rows: a work-group writes 64 consecutive
+// samples (128 bytes) of each transposed intermediate row, whole cache lines
+constexpr int HT_WROW = 2;
+constexpr int HT_WPOS = HT_WPB / HT_WROW;   // and two side by side along the rows
+// samples added to the intermediate's row pitch: with a power-of-two pitch
+// the 32 rows one instruction touches fall on few memory channels
+constexpr int HT_PAD = 8;
+constexpr int HT_G = 16;          // samples per instruction
+constexpr int HT_NR = 4;          // ring slots: sample loads run HT_NR - 1 groups ahead
+constexpr int HT_ARG_TAPS = 880;  // tap words that fit in the kernel arguments
+constexpr int HT_KP_MAX = ((FDVM_MAX_FIR_HALF + 31) / 32) * 32;
+constexpr int HT_NE_MAX = 2 * HT_KP_MAX + 120;
+constexpr size_t HT_TABLE_BYTES = (size_t)FDVM_MAX_SCALES * 2 * HT_NE_MAX * sizeof(u32x4);
+
+enum { SRC_HALF = 0, SRC_U16 = 1, SRC_PAIR = 2 };
+
+// K' = K rounded up to a multiple of 32, so that the groups meeting both
+// output blocks (K'/8 of them) come in whole rounds of the four ring slots
+constexpr int HT_KQ = 32;
+__host__ __device__ constexpr int round_kp(int k) { return ((k + HT_KQ - 1) / HT_KQ) * HT_KQ; }
+__host__ __device__ constexpr int table_entries(int kp) { return 2 * kp + 120; }
+
+struct HalfTaps {   // table builder: taps of one launch's scales, times 2^e, centre first
+    int nscales;
+    int K[FDVM_MAX_SCALES];
+    int off[FDVM_MAX_SCALES];
+    int tab[FDVM_MAX_SCALES];   // table offset, in 16-byte entries
+    float h[HT_ARG_TAPS];
+};
+
+struct HalfSet {    // filter kernel: per scale half-length, table, factor on the sums
+    int nscales;
+    int K[FDVM_MAX_SCALES];
+    int tab[FDVM_MAX_SCALES];
+    float post[FDVM_MAX_SCALES];
+};
+
+template <typename H>
+struct Op;
+template <>
+struct Op<_Float16> {
+    static constexpr float lo_scale = 2048.0f;   // 2^11
+    __device__ static uint16_t bits(float v) { return __builtin_bit_cast(uint16_t, (_Float16)v); }
+    __device__ static float value(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+    __device__ static floatx16 mfma(u32x4 a, u32x4 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                      0, 0, 0);
+    }
+};
+template <>
+struct Op<__bf16> {
+    static constexpr float lo_scale = 256.0f;    // 2^8
+    __device__ static uint16_t bits(float v) { return __builtin_bit_cast(uint16_t, (__bf16)v); }
+    __device__ static float value(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+    __device__ static floatx16 mfma(u32x4 a, u32x4 b, floatx16 c) {
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                       c, 0, 0, 0);
+    }
+};
+
+// v = value(hi) + value(lo) / lo_scale to 2^-2p relative
+template <typename H>
+__device__ __forceinline__ void split(float v, uint16_t &hi, uint16_t &lo) {
+    hi = Op<H>::bits(v);
+    lo = Op<H>::bits((v - Op<H>::value(hi)) * Op<H>::lo_scale);
+}
+
+__device__ __forceinline__ int xcd_logical(int hw, int n) {
+    constexpr int NX = 8;
+    const int xcd = hw % NX, slot = hw / NX;
+    const int q = n / NX, r = n % NX;
+    return xcd * q + min(xcd, r) + slot;
+}
+
+// one work-group per scale: entry e of the scale's table holds taps
+// h(c) .. h(c - 7), c = e - K' - 56 (zero beyond the half-length), hi entries
+// first, then lo'
+template <typename H>
+__global__ __launch_bounds__(256) void fir_half_tables_kernel(u32x4 *__restrict__ tables, HalfTaps ht) {
+    const int s = blockIdx.x;
+    const int K = ht.K[s];
+    const int KP = round_kp(K);
+    const int NE = table_entries(KP);
+    const int C0 = KP + 56;
+    const float *h = ht.h + ht.off[s];
+    u32x4 *tab = tables + ht.tab[s];
+    for (int e = threadIdx.x; e < NE; e += blockDim.x) {
+        uint16_t hi[8], lo[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int d = e - C0 - u;
+            const int ad = d < 0 ? -d : d;
+            split<H>(ad <= K ? h[ad] : 0.0f, hi[u], lo[u]);
+        }
+        u32x4 vh, vl;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            vh[w] = (uint32_t)hi[2 * w] | ((uint32_t)hi[2 * w + 1] << 16);
+            vl[w] = (uint32_t)lo[2 * w] | ((uint32_t)lo[2 * w + 1] << 16);
+        }
+        tab[e] = vh;
+        tab[NE + e] = vl;
+    }
+}
+
+// Filters R rows (plane s of the source, or plane 0 for all scales when
+// src_plane is 0) along their length: n outputs per row from the n_in samples
+// held (n_in >= n: the intermediate's rows carry a padding already filled
+// with the boundary extension); output p of row y goes to
+// dst[p * dst_pitch + y] of plane s for y < R_out: a float32 plane (OUT_F32)
+// or a pair of half planes (hi at dst, lo' at dst_lo), rows y >= R of the
+// pair holding the extension (row R - 1, or zero).  FAST: every group of
+// eight samples lies wholly inside [0, n_in) or wholly outside (n_in a
+// multiple of 8, rows 16-byte aligned): one clamped 16-byte load and a
+// select; otherwise eight clamped element loads.  Neither form branches
+// around a load, so the loads of later groups stay in flight.  Logical blocks
+// (scale, position group, row tile), scale fastest, XCD-contiguous.
+template <typename H, int SRC, bool OUT_F32, bool FAST>
+__global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
+    const uint16_t *__restrict__ src, const uint16_t *__restrict__ src_lo, int64_t src_pitch, int64_t src_plane,
+    int R, int n, int n_in, void *__restrict__ dst, uint16_t *__restrict__ dst_lo, int64_t dst_pitch,
+    int64_t dst_plane, int R_out, int boundary, int vec_out, const u32x4 *__restrict__ tables, HalfSet hs) {
+    constexpr bool SPLIT = SRC != SRC_HALF;   // A carries a lo' part
+    constexpr bool PAIR = SRC == SRC_PAIR;
+    extern __shared__ u32x4 lds[];            // the scale's table: NE hi entries, NE lo' entries
+    const int nrt = (R_out + HT_ROWS * HT_WROW - 1) / (HT_ROWS * HT_WROW);
+    const int npg = (n + HT_POS * HT_WPOS - 1) / (HT_POS * HT_WPOS);
+    const int S = hs.nscales;
+    const int lb = xcd_logical(blockIdx.x, nrt * npg * S);
+    const int s = lb % S;
+    const int pg = (lb / S) % npg;
+    const int rt = lb / (S * npg);
+    const int KP = round_kp(hs.K[s]);
+    const int NE = table_entries(KP);
+    const int NG = KP / 8 + 4;   // groups: 2 K'/16 + 4
+    const int C0 = KP + 56;
+    {
+        const u32x4 *tg = tables + hs.tab[s];
+        for (int e = threadIdx.x; e < 2 * NE; e += blockDim.x) lds[e] = tg[e];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int p0 = (pg * HT_WPOS + wv % HT_WPOS) * HT_POS;
+    const int y0 = (rt * HT_WROW + wv / HT_WPOS) * HT_ROWS;
+    if (p0 >= n || y0 >= R_out) return;   // no barrier follows
+    const int i = lane & 31;   // A: row y0 + i; B and D: output p0 + 32 t + i
+    const int g8 = lane >> 5;  // which eight of the group's sixteen samples
+    const int row = min(y0 + i, R - 1);
+    const bool rep = boundary == FDVM_BC_REPLICATE;
+    const int64_t roff = (int64_t)s * src_plane + (int64_t)row * src_pitch;
+    const uint16_t *rh = src + roff;
+    const uint16_t *rl = PAIR ? src_lo + roff : nullptr;
+    const int cb = p0 - KP + 8 * g8;   // first sample of this lane's eight in group 0
+    auto load = [&](int g, u32x4 &vh, u32x4 &vl) {
+        const int c0 = cb + HT_G * g;
+        if constexpr (FAST) {
+            const int cl = min(max(c0, 0), n_in - 8);
+            vh = *reinterpret_cast<const u32x4 *>(rh + cl);
+            if constexpr (PAIR) vl = *reinterpret_cast<const u32x4 *>(rl + cl);
+        } else {
+            uint32_t eh[8], el[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int cc = min(max(c0 + u, 0), n_in - 1);
+                eh[u] = rh[cc];
+                if constexpr (PAIR) el[u] = rl[cc];
+            }
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                vh[w] = eh[2 * w] | (eh[2 * w + 1] << 16);
+                if constexpr (PAIR) vl[w] = el[2 * w] | (el[2 * w + 1] << 16);
+            }
+        }
+    };
+    // the extension at samples outside [0, n_in): the clamped loads already
+    // replicate in the element form; FAST chunks wholly outside take the
+    // first / last sample of the clamped chunk, or zero
+    auto extend = [&](int g, u32x4 &v) {
+        const int c0 = cb + HT_G * g;
+        if constexpr (FAST) {
+            const bool left = c0 < 0, out = left || c0 >= n_in;
+            uint32_t e = left ? (v[0] & 0xffffu) : (v[3] >> 16);
+            e = rep ? (e | (e << 16)) : 0u;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) v[w] = out ? e : v[w];
+        } else {
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const int c = c0 + 2 * w;
+                const uint32_t m = ((rep || (c >= 0 && c < n_in)) ? 0xffffu : 0u) |
+                                   ((rep || (c + 1 >= 0 && c + 1 < n_in)) ? 0xffff0000u : 0u);
+                v[w] &= m;
+            }
+        }
+    };
+    // uint16 samples -> float16 hi (rounded toward zero, so 65535 stays
+    // finite) and lo' = (x - hi) 2^11, both exact
+    auto split_u16 = [&](const u32x4 &raw, u32x4 &ah, u32x4 &al) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float fa = (float)(raw[w] & 0xffffu), fb = (float)(raw[w] >> 16);
+            const auto hv = __builtin_amdgcn_cvt_pkrtz(fa, fb);
+            const float la = (fa - (float)hv[0]) * 2048.0f, lb2 = (fb - (float)hv[1]) * 2048.0f;
+            const auto lv = __builtin_amdgcn_cvt_pkrtz(la, lb2);
+            ah[w] = __builtin_bit_cast(uint32_t, hv);
+            al[w] = __builtin_bit_cast(uint32_t, lv);
+        }
+    };
+    floatx16 m0, m1, l0, l1;   // hi x hi sums and lo' sums, blocks 0 and 1
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        m0[e] = 0.0f;
+        m1[e] = 0.0f;
+        l0[e] = 0.0f;
+        l1[e] = 0.0f;
+    }
+    // rings: samples of group g in slot g % HT_NR (loaded HT_NR - 1 groups
+    // ahead), block 0's tap fragment of group g in slot g % HT_NR (block 1
+    // uses it two groups later)
+    u32x4 ra[HT_NR], rla[HT_NR], bh[HT_NR], bl[HT_NR];
+#pragma unroll
+    for (int q = 0; q < HT_NR - 1; ++q) load(q, ra[q], rla[q]);
+    const int ebase = C0 + KP + i - 8 * g8;   // block 0's entry at group 0
+    auto step = [&](int g, auto slot_c, auto blocks_c, auto load_c) {
+        constexpr int k = decltype(slot_c)::value;
+        constexpr int BL = decltype(blocks_c)::value;   // 1: block 0, 2: block 1, 3: both
+        if constexpr (decltype(load_c)::value) {
+            constexpr int kn = (k + HT_NR - 1) % HT_NR;
+            load(min(g + HT_NR - 1, NG - 1), ra[kn], rla[kn]);
+        }
+        // keep the loads in this step: the scheduler would otherwise sink
+        // them next to their use three groups later
+        __builtin_amdgcn_sched_barrier(0);
+        u32x4 vh = ra[k], vl, ah, al;
+        extend(g, vh);
+        if constexpr (PAIR) {
+            vl = rla[k];
+            extend(g, vl);
+        }
+        if constexpr (SRC == SRC_U16) {
+            split_u16(vh, ah, al);
+        } else {
+            ah = vh;
+            if constexpr (PAIR) al = vl;
+        }
+        if constexpr (BL & 1) {
+            bh[k] = lds[ebase - HT_G * g];
+            bl[k] = lds[NE + ebase - HT_G * g];
+            m0 = Op<H>::mfma(ah, bh[k], m0);
+            l0 = Op<H>::mfma(ah, bl[k], l0);
+            if constexpr (SPLIT) l0 = Op<H>::mfma(al, bh[k], l0);
+        }
+        if constexpr (BL & 2) {
+            constexpr int q = (k + HT_NR - 2) % HT_NR;
+            m1 = Op<H>::mfma(ah, bh[q], m1);
+            l1 = Op<H>::mfma(ah, bl[q], l1);
+            if constexpr (SPLIT) l1 = Op<H>::mfma(al, bh[q], l1);
+        }
+    };
+    using I = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I3 = std::integral_constant<int, 3>;
+    using LOAD = std::true_type;
+    using NOLOAD = std::false_type;
+    static_assert(HT_NR == 4, "phase slots below assume four ring slots");
+    // block 0 alone for groups 0, 1; both for 2 .. NG - 3 (K'/8 groups, a
+    // multiple of 4); block 1 alone for NG - 2, NG - 1
+    step(0, I{}, I1{}, LOAD{});
+    step(1, I1{}, I1{}, LOAD{});
+    for (int g = 2; g < NG - 2; g += 4) {
+        step(g, I2{}, I3{}, LOAD{});
+        step(g + 1, I3{}, I3{}, LOAD{});
+        step(g + 2, I{}, I3{}, LOAD{});
+        step(g + 3, I1{}, I3{}, LOAD{});
+    }
+    step(NG - 2, I2{}, I2{}, NOLOAD{});
+    step(NG - 1, I3{}, I2{}, NOLOAD{});
+    // D[i][j] of block t sits in lane j + 32 ((i / 4) % 2), register
+    // (i / 8) 4 + i % 4: each lane holds rows y0 + 8 q + 4 g8 + (0..3) of
+    // output p0 + 32 t + (lane & 31)
+    const float post = hs.post[s];
+    constexpr float inv_lo = 1.0f / Op<H>::lo_scale;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int p = p0 + 32 * t + i;
+        if (p >= n) continue;
+        const floatx16 &m = t ? m1 : m0;
+        const floatx16 &l = t ? l1 : l0;
+        const int64_t base = (int64_t)s * dst_plane + (int64_t)p * dst_pitch;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int y = y0 + 8 * q + 4 * g8;
+            float v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                v[u] = (m[4 * q + u] + l[4 * q + u] * inv_lo) * post;
+                if (!OUT_F32 && !rep && y + u >= R) v[u] = 0.0f;   // zero extension rows
+            }
+            if constexpr (OUT_F32) {
+                float *o = static_cast<float *>(dst) + base + y;
+                if (vec_out && y + 3 < R_out) {
+                    *reinterpret_cast<f32x4 *>(o) = f32x4{v[0], v[1], v[2], v[3]};
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (y + u < R_out) o[u] = v[u];
+                }
+            } else {
+                uint16_t hi[4], lo[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) split<H>(v[u], hi[u], lo[u]);
+                uint16_t *oh = static_cast<uint16_t *>(dst) + base + y;
+                uint16_t *ol = dst_lo + base + y;
+                if (y + 3 < R_out) {
+                    *reinterpret_cast<u32x2 *>(oh) =
+                        u32x2{(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+                    *reinterpret_cast<u32x2 *>(ol) =
+                        u32x2{(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (y + u < R_out) {
+                            oh[u] = hi[u];
+                            ol[u] = lo[u];
+                        }
+                }
+            }
+        }
+    }
+}
+
+template <typename H, int SRC, bool OUT_F32, bool FAST>
+hipError_t rows_pass(const void *src, const void *src_lo, int64_t src_pitch, int64_t src_plane, int64_t R,
+                     int64_t n, int64_t n_in, void *dst, void *dst_lo, int64_t dst_pitch, int64_t dst_plane,
+                     int64_t R_out, int boundary, bool vec_out, const u32x4 *tables, const HalfSet &hs, int kp_max,
+                     hipStream_t st) {
+    const unsigned nrt = (unsigned)((R_out + HT_ROWS * HT_WROW - 1) / (HT_ROWS * HT_WROW));
+    const unsigned npg = (unsigned)((n + HT_POS * HT_WPOS - 1) / (HT_POS * HT_WPOS));
+    const size_t lds = sizeof(u32x4) * 2 * (size_t)table_entries(kp_max);
+    hipLaunchKernelGGL((fir_half_rows_kernel<H, SRC, OUT_F32, FAST>), dim3(nrt * npg * (unsigned)hs.nscales),
+                       dim3(HT_WPB * 64), lds, st, static_cast<const uint16_t *>(src),
+                       static_cast<const uint16_t *>(src_lo), src_pitch, src_plane, (int)R, (int)n, (int)n_in, dst,
+                       static_cast<uint16_t *>(dst_lo), dst_pitch, dst_plane, (int)R_out, boundary, (int)vec_out,
+                       tables, hs);
+    return hipGetLastError();
+}
+
+// intermediate planes: W rows (one per frame column) of Hp >= H samples,
+// Hp a multiple of 8 so that every row starts 16-byte aligned
+int64_t pair_pitch(int64_t H) { return ((H + 7) & ~(int64_t)7) + HT_PAD; }
+
+template <typename T, int SRC1>
+hipError_t run_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch, bool vec_in, void *ws, float *out,
+                     int64_t out_pitch, int64_t plane_stride, bool vec_out, const HalfTaps &ht,
+                     const float *unscale, int boundary, hipStream_t st) {
+    constexpr float mid = std::is_same_v<T, _Float16> ? 0.0625f : 1.0f;   // intermediate factor
+    u32x4 *tables = static_cast<u32x4 *>(ws);
+    const int64_t hp = pair_pitch(H);
+    uint16_t *ph = reinterpret_cast<uint16_t *>(static_cast<char *>(ws) + HT_TABLE_BYTES);
+    uint16_t *pl = ph + (int64_t)ht.nscales * W * hp;
+    HalfSet hs{};
+    hs.nscales = ht.nscales;
+    int kp_max = 0;
+    for (int q = 0; q < ht.nscales; ++q) {
+        hs.K[q] = ht.K[q];
+        hs.tab[q] = ht.tab[q];
+        hs.post[q] = unscale[q] * mid;
+        kp_max = round_kp(ht.K[q]) > kp_max ? round_kp(ht.K[q]) : kp_max;
+    }
+    hipLaunchKernelGGL(fir_half_tables_kernel<T>, dim3(ht.nscales), dim3(256), 0, st, tables, ht);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // first pass: the frame's H rows of W samples -> W x hp pair planes, rows
+    // H .. hp - 1 holding the extension; the 16-byte form needs aligned rows
+    // of a multiple of 8 samples
+    if (vec_in && W % 8 == 0)
+        e = rows_pass<T, SRC1, false, true>(in, nullptr, in_pitch, 0, H, W, W, ph, pl, hp, W * hp, hp, boundary,
+                                            true, tables, hs, kp_max, st);
+    else
+        e = rows_pass<T, SRC1, false, false>(in, nullptr, in_pitch, 0, H, W, W, ph, pl, hp, W * hp, hp, boundary,
+                                             true, tables, hs, kp_max, st);
+    if (e != hipSuccess) return e;
+    // second pass: W rows of hp samples (H outputs each) -> the H x W planes
+    for (int q = 0; q < ht.nscales; ++q) hs.post[q] = unscale[q] / mid;
+    return rows_pass<T, SRC_PAIR, true, true>(ph, pl, hp, W * hp, W, H, hp, out, nullptr, out_pitch, plane_stride,
+                                              W, boundary, vec_out, tables, hs, kp_max, st);
+}
+
+}  // namespace
+
+size_t fir_mfma_half_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    return HT_TABLE_BYTES + (size_t)nscales * (size_t)W * (size_t)pair_pitch(H) * 4;
+}
+
+hipError_t launch_fir_mfma_half(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, void *ws,
+                                float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                                const int32_t *half_len, const int32_t *tap_offset, int nscales, int boundary,
+                                hipStream_t st) {
+    if (dtype != FDVM_F16 && dtype != FDVM_BF16 && dtype != FDVM_U16) return hipErrorInvalidValue;
+    const bool vec_in = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && ((in_pitch * 2) % 16 == 0);
+    for (int s0 = 0; s0 < nscales;) {
+        // the longest run of scales whose taps fit in the builder's arguments
+        HalfTaps ht{};
+        float unscale[FDVM_MAX_SCALES];
+        int pos = 0, tab = 0, q = 0;
+        while (s0 + q < nscales && pos + half_len[s0 + q] + 1 <= HT_ARG_TAPS) {
+            const int K = half_len[s0 + q];
+            const double *hd = taps + tap_offset[s0 + q];
+            double hmax = 0.0;
+            for (int m = 0; m <= K; ++m) hmax = std::fmax(hmax, std::fabs(hd[K + m]));
+            int ex = 0;
+            if (hmax > 0.0) std::frexp(hmax, &ex);   // hmax = f 2^ex, f in [0.5, 1)
+            unscale[q] = std::ldexp(1.0f, ex);
+            ht.K[q] = K;
+            ht.off[q] = pos;
+            ht.tab[q] = tab;
+            for (int m = 0; m <= K; ++m) ht.h[pos + m] = (float)std::ldexp(hd[K + m], -ex);
+            pos += K + 1;
+            tab += 2 * table_entries(round_kp(K));
+            ++q;
+        }
+        if (q == 0) return hipErrorInvalidValue;   // a half-length beyond the argument table
+        ht.nscales = q;
+        float *o = out + (int64_t)s0 * plane_stride;
+        const bool vec_out = (reinterpret_cast<uintptr_t>(o) % 16 == 0) && (out_pitch % 4 == 0) &&
+                             (plane_stride % 4 == 0);
+        hipError_t e;
+        if (dtype == FDVM_F16)
+            e = run_chunk<_Float16, SRC_HALF>(in, H, W, in_pitch, vec_in, ws, o, out_pitch, plane_stride, vec_out,
+                                              ht, unscale, boundary, st);
+        else if (dtype == FDVM_U16)
+            e = run_chunk<_Float16, SRC_U16>(in, H, W, in_pitch, vec_in, ws, o, out_pitch, plane_stride, vec_out,
+                                             ht, unscale, boundary, st);
+        else
+            e = run_chunk<__bf16, SRC_HALF>(in, H, W, in_pitch, vec_in, ws, o, out_pitch, plane_stride, vec_out,
+                                            ht, unscale, boundary, st);
+        if (e != hipSuccess) return e;
+        s0 += q;
+    }
+    return hipSuccess;
+}
+
+}  // namespace fdvm

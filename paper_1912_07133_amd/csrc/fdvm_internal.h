@@ -147,6 +147,16 @@ hipError_t launch_fir_mfma(const void *in, int dtype, int64_t H, int64_t W, int6
                            float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
                            const int32_t *half_len, const int32_t *tap_offset, int nscales, int boundary,
                            hipStream_t stream);
+// The same Toeplitz-block FIR with half-precision operands (float16 /
+// bfloat16 frames as stored, uint16 frames split exactly into float16 pairs;
+// taps and the intermediate split hi + scaled lo), float32 accumulation.
+// Workspace: the tap tables and the transposed pair planes of the
+// intermediate.
+size_t fir_mfma_half_workspace_bytes(int64_t H, int64_t W, int nscales);
+hipError_t launch_fir_mfma_half(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, void *ws,
+                                float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                                const int32_t *half_len, const int32_t *tap_offset, int nscales, int boundary,
+                                hipStream_t stream);
 size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half);
 hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
                       float *out, int64_t out_pitch, int64_t plane_stride,

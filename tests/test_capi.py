@@ -125,6 +125,11 @@ def test_device_calls_validate_on_the_host():
                            None) == P.EINVAL
     sym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.1)
     assert L.fdvm_blur_fir(fake, P.F32, 8, 8, 8, fake, 8, 64, sym, half, off, 1, 0, 0, fake, 4, None) == P.ENOMEM
+    # half-precision matrix-core operands: float16, bfloat16 and uint16 frames
+    assert L.fdvm_blur_fir(fake, P.F32, 8, 8, 8, fake, 8, 64, sym, half, off, 1, 0, P.FIR_TOEPLITZ_MFMA_HALF,
+                           fake, 1 << 20, None) == P.EINVAL
+    assert L.fdvm_blur_fir(fake, P.F16, 8, 8, 8, fake, 8, 64, sym, half, off, 1, 0, 3, fake, 1 << 20,
+                           None) == P.EINVAL
 
 
 def test_workspace_sizes():
