@@ -425,6 +425,66 @@ def colored_sg_taps(sigma: float, K: int | None = None, omega_c: float | None = 
     return np.array([c[abs(m)] for m in range(-K, K + 1)])
 
 
+def gaussian_taps_dsigma(sigma: float, K: int) -> np.ndarray:
+    """d h / d sigma of gaussian_taps(sigma, K) at fixed K.  With
+    g(m) = exp(-m^2 / (2 sigma^2)) (Eq 9c; its 1/(sigma sqrt(2 pi)) factor
+    cancels in the renormalisation of Eq 11) and h = g / sum g:
+        dg(m)/dsigma = g(m) m^2 / sigma^3,
+        dh(m)/dsigma = h(m) (m^2 - sum_j h(j) j^2) / sigma^3.
+    Returns dh[0..2K] = dh(-K..K)."""
+    h = gaussian_taps(sigma, K)
+    m2 = np.arange(-K, K + 1, dtype=np.float64) ** 2
+    return h * (m2 - np.sum(h * m2)) / sigma ** 3
+
+
+def colored_sg_taps_dsigma(sigma: float, K: int | None = None, L_D: int = 1) -> np.ndarray:
+    """d h / d sigma of colored_sg_taps(sigma, K) at fixed K with
+    omega_c = 3 / sigma (Section 4.2).  The taps solve the Lagrange system of
+    Eq 20,  [S F^T; F 0] [c; lambda] = [0; rho],  in which only S depends on
+    sigma, through omega_c in Sbar (Eq 22b):
+        d Sbar(d) / d omega_c = -cos(omega_c d) / pi   (d = 0 included),
+        d omega_c / d sigma   = -3 / sigma^2.
+    Differentiating the system,  [S F^T; F 0] [dc; dlambda] = [-dS c; 0],
+    so F dc = 0: the dc gain and second moment stay fixed.
+    Returns dh[0..2K] = dh(-K..K)."""
+    if K is None:
+        K = fir_half_length(sigma, "3sigma")
+    omega_c = 3.0 / sigma
+    domega = -3.0 / (sigma * sigma)
+    M = 2 * K + 1
+    n_k = K + 1
+    idx = np.arange(-K, K + 1)
+    dm = (idx[:, None] - idx[None, :]).astype(np.float64)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        off = -np.sin(omega_c * dm) / dm
+    Sbar = np.where(dm == 0, math.pi - omega_c, off) / math.pi
+    dSbar = -np.cos(omega_c * dm) / math.pi * domega
+    T = np.zeros((n_k, M))
+    for m1 in range(-K, K + 1):
+        T[abs(m1), K + m1] = 1.0
+    S = T @ Sbar @ T.T
+    dS = T @ dSbar @ T.T
+    lbar = L_D + 1
+    mu = np.ones(n_k)
+    mu[0] = 0.5
+    k = np.arange(n_k, dtype=np.float64)
+    F = np.zeros((lbar, n_k))
+    for lb in range(lbar):
+        l = 2 * lb
+        kl = np.where(k == 0, 1.0 if l == 0 else 0.0, k ** l)
+        F[lb] = 2.0 * mu * (-1.0) ** lb * kl
+    rho = np.zeros(lbar)
+    rho[0] = 1.0
+    kkt = np.zeros((n_k + lbar, n_k + lbar))
+    kkt[:n_k, :n_k] = S
+    kkt[:n_k, n_k:] = F.T
+    kkt[n_k:, :n_k] = F
+    c = np.linalg.solve(kkt, np.concatenate([np.zeros(n_k), rho]))[:n_k]
+    dsol = np.linalg.solve(kkt, np.concatenate([-(dS @ c), np.zeros(lbar)]))
+    dc = dsol[:n_k]
+    return np.array([dc[abs(m)] for m in range(-K, K + 1)])
+
+
 # --------------------------------------------------------------------------
 # High-pass interpolating differentiators (Section 3.1, Eq 8, Table I)
 # --------------------------------------------------------------------------

@@ -135,6 +135,17 @@ def blur_2d_matrix(image: np.ndarray, taps: np.ndarray, boundary: str = "replica
     return fir_matrix(taps, H, boundary) @ (X @ fir_matrix(taps, W, boundary).T)
 
 
+def blur_2d_matrix_adjoint(G: np.ndarray, taps: np.ndarray, boundary: str = "replicate") -> np.ndarray:
+    """The transpose of the separable FIR blur of blur_2d_matrix applied to a
+    plane G:  X_bar = T_H^T G T_W, by definition of the transpose of
+    B = T_H X T_W^T.  With the replicate extension the transposed matrices
+    carry the folded tails (the columns of T for j = 0 and N - 1 collect every
+    tap whose source position was clamped there)."""
+    G = np.asarray(G, dtype=np.float64)
+    H, W = G.shape
+    return fir_matrix(taps, H, boundary).T @ (G @ fir_matrix(taps, W, boundary))
+
+
 def apply_1d(x: np.ndarray, filt, boundary: str, axis: int) -> np.ndarray:
     """Apply an IIR (IIRCoefficients) or FIR (tap array) blur along `axis`."""
     xm = np.moveaxis(np.asarray(x, dtype=np.float64), axis, -1)

@@ -321,3 +321,33 @@ def test_fir_half_length_rules():
     assert design.fir_half_length(64.0) == 192
     assert design.fir_half_length(3.28) == 10
     assert design.fir_half_length(4.0, "5sigma") == 20
+
+
+# ------------------------------------------------ sigma derivatives of the FIR designs
+
+def _central(f, sigma, h):
+    """Fourth-order central difference of f at sigma."""
+    return (-f(sigma + 2 * h) + 8 * f(sigma + h) - 8 * f(sigma - h) + f(sigma - 2 * h)) / (12 * h)
+
+
+@pytest.mark.parametrize("sigma,K", [(0.8, 3), (2.0, 6), (9.5, 29), (40.0, 120)])
+def test_gaussian_taps_dsigma_is_the_derivative(sigma, K):
+    got = design.gaussian_taps_dsigma(sigma, K)
+    ref = _central(lambda s: design.gaussian_taps(s, K), sigma, 1e-3 * sigma)
+    assert np.max(np.abs(got - ref)) <= 1e-8 * np.max(np.abs(ref))
+    assert abs(got.sum()) < 1e-15            # Eq 11 holds at every sigma
+    assert np.allclose(got, got[::-1], rtol=0, atol=1e-18)   # symmetric taps
+
+
+@pytest.mark.parametrize("sigma,K", [(1.2, None), (2.0, 6), (5.4, None), (14.5, 44), (64.0, 192), (10.0, 50)])
+def test_colored_sg_taps_dsigma_is_the_derivative(sigma, K):
+    Kk = K if K is not None else design.fir_half_length(sigma)
+    got = design.colored_sg_taps_dsigma(sigma, Kk)
+    ref = _central(lambda s: design.colored_sg_taps(s, K=Kk), sigma, 1e-3 * sigma)
+    assert np.max(np.abs(got - ref)) <= 2e-6 * np.max(np.abs(ref))
+    m = np.arange(-Kk, Kk + 1, dtype=np.float64)
+    scale = np.sum(np.abs(got)) * max(1.0, Kk * Kk)
+    # the dc constraints rho = [1, 0] hold at every sigma: their derivatives vanish
+    assert abs(got.sum()) <= 1e-12 * np.sum(np.abs(got))
+    assert abs(np.sum(m * m * got)) <= 1e-10 * scale
+    assert np.allclose(got, got[::-1], rtol=0, atol=1e-15 * np.max(np.abs(got)))

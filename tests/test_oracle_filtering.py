@@ -246,3 +246,30 @@ def test_hessian_ellipse_pattern_scale_selection():
         mask2, *_ = shape.detect_hessian(B, sg, 0.035, 0.6, 1)
         got = sorted(zip(*[v.tolist() for v in np.nonzero(mask2)]))
         assert got == sorted((int(cy), int(cx)) for (cy, cx, a, b, ang) in items if a == lam), lam
+
+
+@pytest.mark.parametrize("boundary", ["replicate", "zero"])
+@pytest.mark.parametrize("shape_hw,sigma,K", [((13, 17), 2.0, None), ((8, 29), 4.0, 20), ((1, 9), 1.5, 6),
+                                               ((21, 1), 3.0, 30)])
+def test_fir_adjoint_dot_product_against_brute_force(boundary, shape_hw, sigma, K):
+    """<G x, y> = <x, G^T y> with G the direct 2-D sum over the extended image
+    (independent of the matrices the adjoint is built from), also with taps
+    longer than the frame and single-row / single-column frames."""
+    rng = np.random.default_rng(3 * shape_hw[0] + shape_hw[1])
+    x = rng.standard_normal(shape_hw)
+    y = rng.standard_normal(shape_hw)
+    taps = design.colored_sg_taps(sigma, K=K)
+    lhs = float(np.sum(filtering.brute_force_2d(x, taps, boundary) * y))
+    rhs = float(np.sum(x * filtering.blur_2d_matrix_adjoint(y, taps, boundary)))
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+
+
+def test_fir_adjoint_replicate_folds_tails_onto_edges():
+    """With the replicate extension, the adjoint of a constant-preserving blur
+    preserves the total: sum G^T y = sum y (every output draws unit weight)."""
+    rng = np.random.default_rng(8)
+    y = rng.standard_normal((12, 15))
+    taps = design.gaussian_taps(3.0, 11)
+    assert abs(filtering.blur_2d_matrix_adjoint(y, taps).sum() - y.sum()) < 1e-12
+    zero = filtering.blur_2d_matrix_adjoint(y, taps, "zero")
+    assert abs(zero.sum() - y.sum()) > 1e-3      # the zero extension loses the tails
