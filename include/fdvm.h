@@ -69,8 +69,10 @@ typedef enum {
                                     cascade sections); fdvm_iir_pass only   */
     FDVM_FIR_COLORED_SG = 1,    /* Filter C, Section 4.2 (Eqs 20-22)          */
     FDVM_FIR_GAUSSIAN = 2,      /* Filter A, Eqs 9c and 11                    */
-    FDVM_IIR_BUTTERWORTH = 4    /* Filter E, Section 4.4 (order L_B = 4: one
+    FDVM_IIR_BUTTERWORTH = 4,   /* Filter E, Section 4.4 (order L_B = 4: one
                                    complex-conjugate pole pair per direction) */
+    FDVM_FIR_COLORED_SG_DSIGMA = 5, /* d h / d sigma of Filter C at fixed K   */
+    FDVM_FIR_GAUSSIAN_DSIGMA = 6    /* d h / d sigma of Filter A at fixed K   */
 } fdvm_kind;
 
 typedef enum { FDVM_BC_REPLICATE = 0, FDVM_BC_ZERO = 1 } fdvm_boundary;
@@ -154,6 +156,13 @@ const char *fdvm_status_string(fdvm_status status);
  *     omega_c < pi (sigma > 3/pi), otherwise the stopband of Eq 21 is empty
  *     and the call returns FDVM_ERANGE;
  *     kind = FDVM_FIR_GAUSSIAN: Eq 9c sampled on m = -K..K, normalised by Eq 11.
+ *     kind = FDVM_FIR_COLORED_SG_DSIGMA / FDVM_FIR_GAUSSIAN_DSIGMA: the
+ *     derivatives d h(m) / d sigma of those two designs at fixed K (same K
+ *     rule and ranges): the Gaussian's in closed form, h(m) (m^2 - sum_j
+ *     h(j) j^2) / sigma^3; the coloured SG's from the Lagrange system of
+ *     Eq 20 differentiated through Sbar (Eq 22b), omega_c = 3/sigma (only S
+ *     depends on sigma, so the dc constraints hold: sum dh = 0 and
+ *     sum m^2 dh = 0).  b0 receives dh(0)/dsigma.
  *     Half-length K = fir_half_len if > 0, else ceil(3 sigma) (length
  *     6 sigma + 1).  K must be in [1, FDVM_MAX_FIR_HALF]; sigma in [0.25, 1024].
  *     taps (host, float64, capacity taps_cap >= 2K + 1) receives
@@ -353,10 +362,71 @@ fdvm_status fdvm_plane_dots(const float *a, const float *b, int64_t H, int64_t W
                             int64_t plane_stride, int nscales, double *out_dev, void *ws, size_t ws_bytes,
                             void *stream);
 
+/* ------------------------------------------------------------------ backward
+ * Gradients of a loss L through the detection response of a batch of
+ * nframes frames of one size,
+ *     V_s = sigma_s^2 (D20 + D02)(B_s),   B_s = G_s x
+ * (fdvm_iir_laplacian / fdvm_fir_laplacian), given gV = dL/dV:
+ *     gB_s     = sigma_s^2 Lap^T gV_s                     (as fdvm_laplacian_adjoint)
+ *     gx       = sum_s G_s^T gB_s                         (what & FDVM_GRAD_X)
+ *     gsigma_s = sum over frames of
+ *                2/sigma_s <gV_s, V_s> + <gB_s, dB_s/dsigma_s>   (what & FDVM_GRAD_SIGMA)
+ * For the separable blur dB_s/dsigma = (G'_y G_x + G_y G'_x) x, G' the pass
+ * with the sigma-derivative filter (the extension does not depend on sigma).
+ * All of it runs on the device in float32 planes with float64 inner
+ * products (fixed summation order: deterministic); nothing is copied to the
+ * host and the call does not synchronise.
+ *   x        device, frame f at x + f * x_frame_stride elements (dt, row
+ *            pitch x_pitch); read only for FDVM_GRAD_SIGMA (may be NULL
+ *            otherwise).
+ *   V, gV    device float32; frame f, scale s, pixel (y, x) at
+ *            [f * v_frame_stride + s * plane_stride + y * pitch + x]; V is
+ *            read only for FDVM_GRAD_SIGMA (may be NULL otherwise).
+ *   gx       device float32, frame f pixel (y, x) at
+ *            [f * gx_frame_stride + y * gx_pitch + x], overwritten
+ *            (FDVM_GRAD_X; may be NULL otherwise).  Must not overlap the
+ *            inputs.
+ *   gsigma   device float64 [nscales], overwritten with the batch sum
+ *            (FDVM_GRAD_SIGMA; may be NULL otherwise).
+ *   ws       device workspace >= fdvm_workspace_bytes(
+ *            FDVM_OP_IIR_LAPLACIAN_BACKWARD / FDVM_OP_FIR_LAPLACIAN_BACKWARD,
+ *            H, W, nscales, max K), reused frame after frame.
+ * Errors as the forward calls; what = 0 or any other bit is FDVM_EINVAL.
+ */
+enum { FDVM_GRAD_X = 1, FDVM_GRAD_SIGMA = 2 };
+
+/* IIR form (Sections 4.3 and 5: the transposes of the recursions of Eqs
+ * A6-A10 with the replicate start of Eq A32, as fdvm_blur_iir_adjoint, and the
+ * sigma-derivative cascade of fdvm_iir_pass).  filters: FDVM_IIR_REPEATED_POLE designs of
+ * one order; their sigma derivatives are designed inside the call
+ * (FDVM_IIR_REPEATED_POLE_DSIGMA).  Butterworth designs: FDVM_EUNSUPPORTED. */
+fdvm_status fdvm_iir_laplacian_backward(const void *x, fdvm_dtype dt, int64_t H, int64_t W, int64_t x_pitch,
+                                        int64_t x_frame_stride, const float *V, const float *gV, int64_t pitch,
+                                        int64_t plane_stride, int64_t v_frame_stride, int nframes,
+                                        const fdvm_filter *filters, int nscales, fdvm_boundary bc, unsigned what,
+                                        float *gx, int64_t gx_pitch, int64_t gx_frame_stride, double *gsigma,
+                                        void *ws, size_t ws_bytes, void *stream);
+
+/* FIR form (Eq A5 transposed: the zero-extension FIR of the symmetric taps
+ * plus, for the replicate extension, the folded tails sum_m g(m) T(m),
+ * T(m) = sum_{k>m} h(k), added to the first and last sample of every column
+ * and row).  taps / half_len / tap_offset: host, as fdvm_blur_fir;
+ * dtaps: host, dh/dsigma in the same layout (fdvm_filter_design with
+ * FDVM_FIR_COLORED_SG_DSIGMA / FDVM_FIR_GAUSSIAN_DSIGMA; needed only for
+ * FDVM_GRAD_SIGMA); sigmas: host, the scales of the sigma^2 factor. */
+fdvm_status fdvm_fir_laplacian_backward(const void *x, fdvm_dtype dt, int64_t H, int64_t W, int64_t x_pitch,
+                                        int64_t x_frame_stride, const float *V, const float *gV, int64_t pitch,
+                                        int64_t plane_stride, int64_t v_frame_stride, int nframes,
+                                        const double *taps, const double *dtaps, const int32_t *half_len,
+                                        const int32_t *tap_offset, const double *sigmas, int nscales,
+                                        fdvm_boundary bc, unsigned what, float *gx, int64_t gx_pitch,
+                                        int64_t gx_frame_stride, double *gsigma, void *ws, size_t ws_bytes,
+                                        void *stream);
+
 /* workspace sizes */
 enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3,
        FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5, FDVM_OP_IIR_HESSIAN = 6,
-       FDVM_OP_FIR_LAPLACIAN = 7 };
+       FDVM_OP_FIR_LAPLACIAN = 7, FDVM_OP_IIR_LAPLACIAN_BACKWARD = 8, FDVM_OP_FIR_LAPLACIAN_BACKWARD = 9 };
 
 /* Bytes of device workspace `op` needs for an H x W frame with nscales
  * scales and maximum FIR half-length max_half_len (0 if unused). */

@@ -207,15 +207,14 @@ Cascade sigma_derivative_realisation(int K, double sigma) {
 //   Sbar(d) = (pi - omega_c)/pi (d = 0),  -sin(omega_c d)/(pi d) (d != 0).
 // Solved through the Schur complement: Y = S^-1 F^T (Cholesky), then
 // lambda = (F Y)^-1 rho and c = Y lambda, in long double.
-int colored_sg_taps(double sigma, int K, double omega_c, double *taps) {
-    (void)sigma;
-    typedef long double ld;
+namespace {
+typedef long double ld;
+const ld PI_L = 3.141592653589793238462643383279502884L;
+
+// S (or, with dsbar, d S / d omega_c) of the K + 1 pair coefficients
+template <class F>
+std::vector<ld> pair_matrix(int K, F sbar) {
     const int n = K + 1;
-    const ld pi = 3.141592653589793238462643383279502884L;
-    auto sbar = [&](int d) -> ld {
-        if (d == 0) return (pi - (ld)omega_c) / pi;
-        return -std::sin((ld)omega_c * (ld)d) / (pi * (ld)d);
-    };
     std::vector<ld> S((size_t)n * n, 0.0L);
     for (int k1 = 0; k1 < n; ++k1) {
         for (int k2 = 0; k2 < n; ++k2) {
@@ -230,50 +229,110 @@ int colored_sg_taps(double sigma, int K, double omega_c, double *taps) {
             S[(size_t)k1 * n + k2] = acc;
         }
     }
-    // Cholesky S = L L^T (in place, lower triangle)
-    for (int j = 0; j < n; ++j) {
-        ld d = S[(size_t)j * n + j];
-        for (int k = 0; k < j; ++k) d -= S[(size_t)j * n + k] * S[(size_t)j * n + k];
-        if (!(d > 0.0L)) return -1;
-        d = std::sqrt(d);
-        S[(size_t)j * n + j] = d;
-        for (int i = j + 1; i < n; ++i) {
-            ld s = S[(size_t)i * n + j];
-            for (int k = 0; k < j; ++k) s -= S[(size_t)i * n + k] * S[(size_t)j * n + k];
-            S[(size_t)i * n + j] = s / d;
-        }
-    }
-    auto solve = [&](std::vector<ld> &v) {
+    return S;
+}
+
+struct SgSystem {
+    int n;
+    std::vector<ld> L;        // Cholesky factor of S (lower triangle)
+    std::vector<ld> y0, y2;   // S^-1 f0, S^-1 f2
+    std::vector<ld> f0, f2;   // the rows of F
+    ld m00, m01, m11;         // F Y
+    std::vector<ld> c;        // the solution
+
+    void solve(std::vector<ld> &v) const {
         for (int i = 0; i < n; ++i) {
             ld s = v[i];
-            for (int k = 0; k < i; ++k) s -= S[(size_t)i * n + k] * v[k];
-            v[i] = s / S[(size_t)i * n + i];
+            for (int k = 0; k < i; ++k) s -= L[(size_t)i * n + k] * v[k];
+            v[i] = s / L[(size_t)i * n + i];
         }
         for (int i = n - 1; i >= 0; --i) {
             ld s = v[i];
-            for (int k = i + 1; k < n; ++k) s -= S[(size_t)k * n + i] * v[k];
-            v[i] = s / S[(size_t)i * n + i];
+            for (int k = i + 1; k < n; ++k) s -= L[(size_t)k * n + i] * v[k];
+            v[i] = s / L[(size_t)i * n + i];
         }
-    };
-    std::vector<ld> f0(n), f2(n);
-    for (int k = 0; k < n; ++k) {
-        f0[k] = k == 0 ? 1.0L : 2.0L;
-        f2[k] = 2.0L * (ld)k * (ld)k;
     }
-    std::vector<ld> y0 = f0, y2 = f2;
-    solve(y0);
-    solve(y2);
-    ld m00 = 0, m01 = 0, m11 = 0;
-    for (int k = 0; k < n; ++k) {
-        m00 += f0[k] * y0[k];
-        m01 += f0[k] * y2[k];
-        m11 += f2[k] * y2[k];
+
+    bool build(int K, double omega_c) {
+        n = K + 1;
+        L = pair_matrix(K, [&](int d) -> ld {
+            if (d == 0) return (PI_L - (ld)omega_c) / PI_L;
+            return -std::sin((ld)omega_c * (ld)d) / (PI_L * (ld)d);
+        });
+        for (int j = 0; j < n; ++j) {   // Cholesky S = L L^T in place
+            ld d = L[(size_t)j * n + j];
+            for (int k = 0; k < j; ++k) d -= L[(size_t)j * n + k] * L[(size_t)j * n + k];
+            if (!(d > 0.0L)) return false;
+            d = std::sqrt(d);
+            L[(size_t)j * n + j] = d;
+            for (int i = j + 1; i < n; ++i) {
+                ld s = L[(size_t)i * n + j];
+                for (int k = 0; k < j; ++k) s -= L[(size_t)i * n + k] * L[(size_t)j * n + k];
+                L[(size_t)i * n + j] = s / d;
+            }
+        }
+        f0.assign(n, 0.0L);
+        f2.assign(n, 0.0L);
+        for (int k = 0; k < n; ++k) {
+            f0[k] = k == 0 ? 1.0L : 2.0L;
+            f2[k] = 2.0L * (ld)k * (ld)k;
+        }
+        y0 = f0;
+        y2 = f2;
+        solve(y0);
+        solve(y2);
+        m00 = m01 = m11 = 0.0L;
+        for (int k = 0; k < n; ++k) {
+            m00 += f0[k] * y0[k];
+            m01 += f0[k] * y2[k];
+            m11 += f2[k] * y2[k];
+        }
+        const ld det = m00 * m11 - m01 * m01;
+        const ld l0 = m11 / det, l2 = -m01 / det;  // (F Y)^-1 [1, 0]^T
+        c.assign(n, 0.0L);
+        for (int k = 0; k < n; ++k) c[k] = y0[k] * l0 + y2[k] * l2;
+        return true;
     }
-    const ld det = m00 * m11 - m01 * m01;
-    const ld l0 = m11 / det, l2 = -m01 / det;  // (F Y)^-1 [1, 0]^T
+};
+}  // namespace
+
+int colored_sg_taps(double sigma, int K, double omega_c, double *taps) {
+    (void)sigma;
+    SgSystem sys;
+    if (!sys.build(K, omega_c)) return -1;
+    for (int m = -K; m <= K; ++m) taps[m + K] = (double)sys.c[m < 0 ? -m : m];
+    return 0;
+}
+
+// d h / d sigma of the coloured SG blur at fixed K, omega_c = 3 / sigma.
+// Only S depends on sigma; differentiating S c + F^T lambda = 0, F c = rho:
+//   S dc + F^T dlambda = -dS c,  F dc = 0,
+// so with z = S^-1 (dS c):  dlambda = -(F Y)^-1 F z,  dc = -z - Y dlambda.
+// dS = T dSbar T^T, dSbar(d) = -cos(omega_c d) / pi * d omega_c / d sigma.
+int colored_sg_dtaps(double sigma, int K, double omega_c, double *dtaps) {
+    SgSystem sys;
+    if (!sys.build(K, omega_c)) return -1;
+    const int n = K + 1;
+    const ld dw = -3.0L / ((ld)sigma * (ld)sigma);
+    const std::vector<ld> dS = pair_matrix(K, [&](int d) -> ld { return -std::cos((ld)omega_c * (ld)d) / PI_L * dw; });
+    std::vector<ld> z(n, 0.0L);
+    for (int i = 0; i < n; ++i) {
+        ld acc = 0.0L;
+        for (int k = 0; k < n; ++k) acc += dS[(size_t)i * n + k] * sys.c[k];
+        z[i] = acc;
+    }
+    sys.solve(z);
+    ld fz0 = 0.0L, fz2 = 0.0L;
+    for (int k = 0; k < n; ++k) {
+        fz0 += sys.f0[k] * z[k];
+        fz2 += sys.f2[k] * z[k];
+    }
+    const ld det = sys.m00 * sys.m11 - sys.m01 * sys.m01;
+    const ld u0 = (sys.m11 * fz0 - sys.m01 * fz2) / det;   // (F Y)^-1 F z = -dlambda
+    const ld u2 = (-sys.m01 * fz0 + sys.m00 * fz2) / det;
     for (int m = -K; m <= K; ++m) {
         const int k = m < 0 ? -m : m;
-        taps[m + K] = (double)(y0[k] * l0 + y2[k] * l2);
+        dtaps[m + K] = (double)(-z[k] + sys.y0[k] * u0 + sys.y2[k] * u2);
     }
     return 0;
 }
@@ -286,6 +345,18 @@ int gaussian_taps(double sigma, int K, double *taps) {
         sum += taps[m + K];
     }
     for (int m = -K; m <= K; ++m) taps[m + K] /= sum;
+    return 0;
+}
+
+// d h / d sigma of the sampled Gaussian at fixed K: with g(m) =
+// exp(-m^2 / (2 sigma^2)) and h = g / sum g, dh(m) = h(m) (m^2 - sum_j h(j) j^2)
+// / sigma^3.
+int gaussian_dtaps(double sigma, int K, double *dtaps) {
+    gaussian_taps(sigma, K, dtaps);
+    double mom = 0.0;
+    for (int m = -K; m <= K; ++m) mom += dtaps[m + K] * (double)m * m;
+    const double s3 = sigma * sigma * sigma;
+    for (int m = -K; m <= K; ++m) dtaps[m + K] *= ((double)m * m - mom) / s3;
     return 0;
 }
 

@@ -71,6 +71,20 @@ def test_fir_length_override_and_gaussian():
     assert np.max(np.abs(g - design.gaussian_taps(4.0, 20))) < 1e-15
 
 
+@pytest.mark.parametrize("sigma,K", [(2.0, 0), (5.4, 0), (23.8, 0), (64.0, 0), (10.0, 40)])
+def test_fir_dsigma_designs_match_oracle(sigma, K):
+    """d h / d sigma of the coloured SG (Lagrange system of Eq 20
+    differentiated) and of the sampled Gaussian, at fixed K."""
+    Kk = K if K else math.ceil(3 * sigma - 1e-9)
+    got = P.filter_design(P.FIR_COLORED_SG_DSIGMA, sigma, fir_half_len=K)
+    ref = design.colored_sg_taps_dsigma(sigma, Kk)
+    assert got["ntaps"] == 2 * Kk + 1
+    assert np.max(np.abs(got["taps"] - ref)) <= 1e-7 * np.max(np.abs(ref))
+    assert got["b0"] == got["taps"][Kk]
+    g = P.filter_design(P.FIR_GAUSSIAN_DSIGMA, sigma, fir_half_len=K)["taps"]
+    assert np.max(np.abs(g - design.gaussian_taps_dsigma(sigma, Kk))) <= 1e-12 * np.max(np.abs(g))
+
+
 def test_design_errors():
     L = P.lib()
     f = P.Filter()
@@ -306,3 +320,46 @@ def test_batch_validates_every_frame_before_enqueueing():
     filt = P.iir_designs([2.0, 4.0])
     st = L.fdvm_batch_detect(frames, 3, filt, 2, P.BC_REPLICATE, 1.0, 1, 2, ctypes.c_void_p(4096), 1 << 40, None)
     assert st == P.EINVAL
+
+
+def test_backward_validation():
+    """Argument checks of the two backward calls, before any device work."""
+    L = P.lib()
+    fake = ctypes.c_void_p(4096)
+    f = (P.Filter * 2)()
+    for i, sg in enumerate((2.0, 4.0)):
+        assert L.fdvm_filter_design(P.IIR_REPEATED_POLE, 3, sg, 0, ctypes.byref(f[i]), None, 0) == P.OK
+    bw = (P.Filter * 1)()
+    assert L.fdvm_filter_design(P.IIR_BUTTERWORTH, 4, 4.0, 0, ctypes.byref(bw[0]), None, 0) == P.OK
+    big = 1 << 40
+    other = ctypes.c_void_p(1 << 20)   # gx must not be gV
+
+    def iir(what=P.GRAD_X, nframes=1, filt=f, S=2, ws=fake, wsb=big, gx=other, gs=fake):
+        return L.fdvm_iir_laplacian_backward(fake, P.F32, 16, 16, 16, 256, fake, fake, 16, 256, 512, nframes, filt,
+                                             S, 0, what, gx, 16, 256, gs, ws, wsb, None)
+
+    assert iir(what=0) == P.EINVAL
+    assert iir(what=4) == P.EINVAL
+    assert iir(nframes=0) == P.EINVAL
+    assert iir(ws=None) == P.EINVAL
+    assert iir(gx=None) == P.EINVAL
+    assert iir(gx=fake) == P.EINVAL      # gx overlapping gV
+    assert iir(what=P.GRAD_SIGMA, gs=None) == P.EINVAL
+    assert iir(filt=bw, S=1) == P.EUNSUPPORTED
+    assert iir(wsb=16) == P.ENOMEM
+    half = (ctypes.c_int32 * 1)(2)
+    off = (ctypes.c_int32 * 1)(0)
+    sig = (ctypes.c_double * 1)(1.0)
+    sym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.1)
+    asym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.11)
+
+    def fir(taps=sym, dtaps=sym, what=P.GRAD_X, wsb=big, s=sig):
+        return L.fdvm_fir_laplacian_backward(fake, P.F32, 16, 16, 16, 256, fake, fake, 16, 256, 256, 1, taps, dtaps,
+                                             half, off, s, 1, 0, what, other, 16, 256, fake, fake, wsb, None)
+
+    assert fir(taps=asym) == P.EINVAL
+    assert fir(what=P.GRAD_SIGMA, dtaps=None) == P.EINVAL
+    assert fir(s=(ctypes.c_double * 1)(-1.0)) == P.ERANGE
+    assert fir(wsb=16) == P.ENOMEM
+    assert P.workspace_bytes(P.OP_IIR_LAPLACIAN_BACKWARD, 1024, 1024, 4) >= 3 * 4 * 1024 * 1024 * 4
+    assert P.workspace_bytes(P.OP_FIR_LAPLACIAN_BACKWARD, 1024, 1024, 4) >= 7 * 1024 * 1024 * 4
