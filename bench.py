@@ -182,51 +182,55 @@ def run_batch_leg(P, syn, torch, np, dev, stream, log):
 
 def run_grad_leg(P, syn, torch, np, dev, stream, log):
     """16 float32 frames of 1024 x 1024 (the full-frame generator / 4095,
-    50 blobs each, seeds 500 + f), sigma = 3, 6, 12, 24 learnable: the fused
-    blur + normalised Laplacian forward and the hand-written backward (image and
-    sigma) of loss = sum over the detected centres of V^2, one frame after the
-    other; Mpixel*scales/s of forward + backward."""
+    50 blobs each, seeds 500 + f) as one batch, sigma = 3, 6, 12, 24
+    learnable: the blur + normalised Laplacian forward (frame after frame) and
+    the backward of loss = sum over the detected centres of V^2 in the image
+    and sigma, one fdvm_*_laplacian_backward call for the batch; Mpixel*scales/s
+    of forward + backward, IIR (the C5 step) and the FIR form beside it."""
     cfg = syn.DIFFERENTIATION
     sig = cfg["sigmas"]
-    frames = [torch.from_numpy(syn.normalised_frame(cfg["H"], cfg["W"], 500 + f, nblobs=cfg["nblobs"])
-                               .astype(np.float32)).to(dev) for f in range(cfg["frames"])]
-    centres = []
-    for x in frames:
-        det = P.detect_blobs(P.iir_laplacian(x, sig), 0.02, 1)
-        c = torch.tensor([(int(d["scale"]), int(d["y"]), int(d["x"])) for d in det], dtype=torch.long, device=dev)
-        centres.append(c)
+    X = torch.stack([torch.from_numpy(syn.normalised_frame(cfg["H"], cfg["W"], 500 + f, nblobs=cfg["nblobs"])
+                                      .astype(np.float32)) for f in range(cfg["frames"])]).to(dev)
+    cs = []
+    for f in range(cfg["frames"]):
+        det = P.detect_blobs(P.iir_laplacian(X[f], sig), 0.02, 1)
+        cs += [(f, int(d["scale"]), int(d["y"]), int(d["x"])) for d in det]
+    c = torch.tensor(cs, dtype=torch.long, device=dev)
 
-    def step():
-        sig_t = torch.tensor(sig, dtype=torch.float64, device=dev, requires_grad=True)
-        total = 0.0
-        for x, c in zip(frames, centres):
-            xr = x.requires_grad_(True)
-            V = P.iir_laplacian_grad(xr, sig_t)
-            loss = (V[c[:, 0], c[:, 1], c[:, 2]].double() ** 2).sum()
+    def make_step(fn):
+        def step():
+            sig_t = torch.tensor(sig, dtype=torch.float64, device=dev, requires_grad=True)
+            xr = X.detach().requires_grad_(True)
+            V = fn(xr, sig_t)
+            loss = (V[c[:, 0], c[:, 1], c[:, 2], c[:, 3]].double() ** 2).sum()
             loss.backward()
-            total = total + loss.detach()
-        return sig_t.grad
+            return sig_t.grad
+        return step
 
-    for _ in range(3):
-        step()
-    torch.cuda.synchronize()
-    reps = 5
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_wall = time.perf_counter()
-    e0.record(stream)
-    for _ in range(reps):
-        g = step()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall_ms = (time.perf_counter() - t_wall) * 1e3 / reps
-    ms = e0.elapsed_time(e1) / reps
+    def timed(step, reps=5):
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t_wall = time.perf_counter()
+        e0.record(stream)
+        for _ in range(reps):
+            g = step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, (time.perf_counter() - t_wall) * 1e3 / reps, g
+
     mpx = cfg["frames"] * cfg["H"] * cfg["W"] * len(sig) / 1e6
+    ms, wall_ms, g = timed(make_step(P.iir_laplacian_grad))
     out = {"workload": cfg["name"], "ms_fwd_bwd": round(ms, 3), "value": round(mpx / (ms / 1e3), 1),
            "unit": "Mpixel·scales/s (forward + backward)", "dL_dsigma": [round(float(v), 8) for v in g.cpu()],
-           "centres": int(sum(len(c) for c in centres))}
-    out["wall_ms"] = round(wall_ms, 3)
-    log(f"grad: 16 x 1024^2 x 4 scales forward + backward {ms:.2f} ms (wall {wall_ms:.2f} ms) = "
-        f"{out['value']:.0f} Mpx*scales/s")
+           "centres": len(cs), "wall_ms": round(wall_ms, 3), "batch": "one backward call for the 16 frames"}
+    fms, fwall, fg = timed(make_step(P.fir_laplacian_grad))
+    out["fir"] = {"ms_fwd_bwd": round(fms, 3), "value": round(mpx / (fms / 1e3), 1), "wall_ms": round(fwall, 3),
+                  "dL_dsigma": [round(float(v), 8) for v in fg.cpu()],
+                  "form": "coloured SG, K = ceil(3 sigma), float64 FIR forward, float32 backward"}
+    log(f"grad: 16 x 1024^2 x 4 scales forward + backward IIR {ms:.2f} ms (wall {wall_ms:.2f} ms) = "
+        f"{out['value']:.0f} Mpx*scales/s; FIR {fms:.2f} ms = {out['fir']['value']:.0f}")
     return out
 
 

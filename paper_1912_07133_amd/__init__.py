@@ -26,6 +26,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "fdvm.h")
 # enums (include/fdvm.h)
 OK, EINVAL, ERANGE, ENOMEM, EDEVICE, EOVERFLOW, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 IIR_REPEATED_POLE, FIR_COLORED_SG, FIR_GAUSSIAN, IIR_REPEATED_POLE_DSIGMA, IIR_BUTTERWORTH = 0, 1, 2, 3, 4
+FIR_COLORED_SG_DSIGMA, FIR_GAUSSIAN_DSIGMA = 5, 6
 # `order` of the IIR calls: 2 or 3 (repeated pole, Filter D) or BUTTERWORTH
 # (the L_B = 4 Butterworth blur, Filter E)
 BUTTERWORTH = "butterworth"
@@ -34,12 +35,15 @@ U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA, FIR_TOEPLITZ_MFMA_HALF = 0, 1, 2
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
 (OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN,
- OP_FIR_LAPLACIAN) = range(8)
+ OP_FIR_LAPLACIAN, OP_IIR_LAPLACIAN_BACKWARD, OP_FIR_LAPLACIAN_BACKWARD) = range(10)
+GRAD_X, GRAD_SIGMA = 1, 2
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
 
 KINDS = {"iir": IIR_REPEATED_POLE, "butterworth": IIR_BUTTERWORTH, "sg": FIR_COLORED_SG,
          "colored_sg": FIR_COLORED_SG, "gaussian": FIR_GAUSSIAN}
+# the sigma derivative of each FIR design
+FIR_DSIGMA = {FIR_COLORED_SG: FIR_COLORED_SG_DSIGMA, FIR_GAUSSIAN: FIR_GAUSSIAN_DSIGMA}
 BOUNDARIES = {"replicate": BC_REPLICATE, "zero": BC_ZERO}
 
 
@@ -137,6 +141,14 @@ def lib() -> ctypes.CDLL:
                                              i64, vp]
         L.fdvm_plane_dots.restype = ctypes.c_int
         L.fdvm_plane_dots.argtypes = [vp, vp, i64, i64, i64, i64, ctypes.c_int, vp, vp, ctypes.c_size_t, vp]
+        bwd = [vp, ctypes.c_int, i64, i64, i64, i64, vp, vp, i64, i64, i64, ctypes.c_int]
+        tail = [ctypes.c_int, ctypes.c_uint, vp, i64, i64, vp, vp, ctypes.c_size_t, vp]
+        L.fdvm_iir_laplacian_backward.restype = ctypes.c_int
+        L.fdvm_iir_laplacian_backward.argtypes = bwd + [ctypes.POINTER(Filter), ctypes.c_int] + tail
+        L.fdvm_fir_laplacian_backward.restype = ctypes.c_int
+        L.fdvm_fir_laplacian_backward.argtypes = bwd + [ctypes.POINTER(dbl), ctypes.POINTER(dbl),
+                                                        ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                                        ctypes.POINTER(dbl), ctypes.c_int] + tail
         L.fdvm_batch_workspace_bytes.restype = ctypes.c_size_t
         L.fdvm_batch_workspace_bytes.argtypes = [ctypes.POINTER(Frame), ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.fdvm_batch_detect.restype = ctypes.c_int
@@ -543,42 +555,123 @@ def dblur_dsigma_parts(x, sigmas: Sequence[float], order: int = 3, boundary: str
     return D1, D2
 
 
-def _make_iir_laplacian_fn():
+def _frames3(x):
+    """A frame [H, W] or a batch [N, H, W] (CUDA, unit column stride) as
+    ([N, H, W] view, whether a single frame was given)."""
+    if not x.is_cuda:
+        raise ValueError("frames must be CUDA (HIP) tensors")
+    single = x.dim() == 2
+    x3 = x.unsqueeze(0) if single else x
+    if x3.dim() != 3:
+        raise ValueError("frames must be [H, W] or [N, H, W]")
+    if x3.stride(2) != 1:
+        x3 = x3.contiguous()
+    return x3, single
+
+
+def _response_frames(fwd, x3, S, op):
+    """V [N, S, H, W]: the forward call frame after frame, one workspace."""
+    torch = _torch()
+    N, H, W = x3.shape
+    V = torch.empty((N, S, H, W), dtype=torch.float32, device=x3.device)
+    ws = _workspace(op, H, W, S, x3.device)
+    for f in range(N):
+        fwd(x3[f], out=V[f], workspace=ws)
+    return V
+
+
+def _backward(ctx, gV, call, op, extra):
+    """Marshals one fdvm_*_laplacian_backward call for the whole batch."""
+    torch = _torch()
+    x3, V = ctx.saved_tensors[0], ctx.saved_tensors[1]
+    N, H, W = x3.shape
+    S = V.shape[1]
+    what = (GRAD_X if ctx.needs_input_grad[0] else 0) | (GRAD_SIGMA if ctx.needs_input_grad[1] else 0)
+    if what == 0:
+        return None, None
+    gV = gV.reshape(N, S, H, W).float().contiguous()
+    gx = torch.empty((N, H, W), dtype=torch.float32, device=V.device) if what & GRAD_X else None
+    gs = torch.empty(S, dtype=torch.float64, device=V.device) if what & GRAD_SIGMA else None
+    ws = torch.empty(max(workspace_bytes(op, H, W, S), 1), dtype=torch.uint8, device=V.device)
+    _check(call(x3.data_ptr(), _dtype_code(x3), H, W, x3.stride(1), x3.stride(0), V.data_ptr(), gV.data_ptr(), W,
+                H * W, S * H * W, N, *extra, S, BOUNDARIES[ctx.boundary], what,
+                gx.data_ptr() if gx is not None else None, W, H * W,
+                gs.data_ptr() if gs is not None else None, ws.data_ptr(), ws.numel(), _stream_ptr(V.device)),
+           call.__name__)
+    if gx is not None and ctx.single:
+        gx = gx[0]
+    return gx, gs
+
+
+def _make_grad_fns():
     torch = _torch()
 
     class IirLaplacianFn(torch.autograd.Function):
         """V_s = sigma_s^2 (D20 + D02)(B_s), B_s the repeated-pole blur of x
-        (iir_laplacian), differentiable in x (float32 frame [H, W]) and sigma
-        (float64 tensor [S]) through hand-written adjoint kernels:
-            dL/dB_s     = sigma_s^2 Lap^T dL/dV_s          (laplacian_adjoint)
-            dL/dx       = sum_s G_s^T dL/dB_s              (blur_iir_adjoint)
-            dL/dsigma_s = 2/sigma_s <dL/dV_s, V_s> + <dL/dB_s, dB_s/dsigma_s>
-        with dB_s/dsigma_s from the sigma-derivative recursions."""
+        (iir_laplacian, frame after frame), differentiable in x (float32
+        frames) and sigma (float64 tensor [S]).  The backward is one call of
+        fdvm_iir_laplacian_backward for the batch (transposed Laplacian,
+        transposed blurs summed over the scales, the sigma-derivative
+        recursions and the inner products of dL/dsigma, all on the device)."""
 
         @staticmethod
         def forward(ctx, x, sigma, order=3, boundary="replicate"):
             sig = _host_values(sigma)
-            V = iir_laplacian(x.detach(), sig, order=order, boundary=boundary)
-            ctx.save_for_backward(x, V, sigma.detach())
-            ctx.sig, ctx.order, ctx.boundary = sig, order, boundary
-            return V
+            x3, single = _frames3(x.detach())
+            V = _response_frames(lambda xf, out, workspace: iir_laplacian(xf, sig, order=order, boundary=boundary,
+                                                                          out=out, workspace=workspace),
+                                 x3, len(sig), OP_IIR_LAPLACIAN)
+            ctx.save_for_backward(x3, V)
+            ctx.sig, ctx.boundary, ctx.single = sig, boundary, single
+            ctx.filters = iir_designs(sig, order)
+            ctx.sigma_device, ctx.sigma_dtype = sigma.device, sigma.dtype
+            return V[0] if single else V
 
         @staticmethod
         def backward(ctx, gV):
-            x, V, s = ctx.saved_tensors
-            sig = ctx.sig
-            gV = gV.contiguous().float()
-            gB = laplacian_adjoint(gV, sig)
-            gx = gsig = None
-            if ctx.needs_input_grad[0]:
-                gx = blur_iir_adjoint(gB, sig, ctx.order, ctx.boundary).sum(0)
-            if ctx.needs_input_grad[1]:
-                D1, D2 = dblur_dsigma_parts(x.detach(), sig, ctx.order, ctx.boundary)
-                dots = 2.0 / s.to(device=V.device, dtype=torch.float64) * plane_dots(gV, V)
-                gsig = (dots + plane_dots(gB, D1) + plane_dots(gB, D2)).to(s.device)
-            return gx, gsig, None, None
+            gx, gs = _backward(ctx, gV, lib().fdvm_iir_laplacian_backward, OP_IIR_LAPLACIAN_BACKWARD,
+                               (ctx.filters,))
+            if gs is not None:
+                gs = gs.to(device=ctx.sigma_device, dtype=ctx.sigma_dtype)
+            return gx, gs, None, None
 
-    return IirLaplacianFn
+    class FirLaplacianFn(torch.autograd.Function):
+        """The FIR form (fir_laplacian: the taps of `kind` at the half-lengths
+        half_lens, or K = ceil(3 sigma)); the sigma gradient differentiates the
+        taps at fixed K (fdvm_filter_design's *_DSIGMA kinds).  Backward: one
+        call of fdvm_fir_laplacian_backward for the batch."""
+
+        @staticmethod
+        def forward(ctx, x, sigma, kind="sg", half_lens=None, boundary="replicate"):
+            sig = _host_values(sigma)
+            x3, single = _frames3(x.detach())
+            taps, half, off = fir_taps(kind, sig, half_lens)
+            V = _response_frames(lambda xf, out, workspace: fir_laplacian(xf, sig, kind=kind, half_lens=half,
+                                                                          boundary=boundary, out=out,
+                                                                          workspace=workspace),
+                                 x3, len(sig), OP_FIR_LAPLACIAN)
+            ctx.save_for_backward(x3, V)
+            ctx.sig, ctx.boundary, ctx.single = sig, boundary, single
+            ctx.kind, ctx.taps, ctx.half, ctx.off = kind, np.ascontiguousarray(taps), half, off
+            ctx.sigma_device, ctx.sigma_dtype = sigma.device, sigma.dtype
+            return V[0] if single else V
+
+        @staticmethod
+        def backward(ctx, gV):
+            dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
+            dtaps = None
+            if ctx.needs_input_grad[1]:
+                dkind = FIR_DSIGMA[KINDS[ctx.kind] if isinstance(ctx.kind, str) else int(ctx.kind)]
+                dtaps = np.ascontiguousarray(fir_taps(dkind, ctx.sig, ctx.half)[0])
+            sig = (ctypes.c_double * len(ctx.sig))(*ctx.sig)
+            extra = (ctx.taps.ctypes.data_as(dp), dtaps.ctypes.data_as(dp) if dtaps is not None else None,
+                     ctx.half.ctypes.data_as(ip), ctx.off.ctypes.data_as(ip), sig)
+            gx, gs = _backward(ctx, gV, lib().fdvm_fir_laplacian_backward, OP_FIR_LAPLACIAN_BACKWARD, extra)
+            if gs is not None:
+                gs = gs.to(device=ctx.sigma_device, dtype=ctx.sigma_dtype)
+            return gx, gs, None, None, None
+
+    return IirLaplacianFn, FirLaplacianFn
 
 
 _iir_lap_fn = None
@@ -603,13 +696,25 @@ def _host_values(sigma):
     return vals
 
 
-def iir_laplacian_grad(x, sigma, order: int = 3, boundary: str = "replicate"):
-    """Differentiable iir_laplacian: x float32 [H, W] (requires_grad allowed),
-    sigma float64 tensor [S] (requires_grad allowed) -> V [S, H, W]."""
+def _grad_fns():
     global _iir_lap_fn
     if _iir_lap_fn is None:
-        _iir_lap_fn = _make_iir_laplacian_fn()
-    return _iir_lap_fn.apply(x, sigma, order, boundary)
+        _iir_lap_fn = _make_grad_fns()
+    return _iir_lap_fn
+
+
+def iir_laplacian_grad(x, sigma, order: int = 3, boundary: str = "replicate"):
+    """Differentiable iir_laplacian: x float32 [H, W] or a batch [N, H, W]
+    (requires_grad allowed), sigma float64 tensor [S] (requires_grad allowed)
+    -> V [S, H, W] or [N, S, H, W]."""
+    return _grad_fns()[0].apply(x, sigma, order, boundary)
+
+
+def fir_laplacian_grad(x, sigma, kind: str = "sg", half_lens: Sequence[int] | None = None,
+                       boundary: str = "replicate"):
+    """Differentiable fir_laplacian (same shapes as iir_laplacian_grad); the
+    sigma gradient is taken at fixed half-lengths."""
+    return _grad_fns()[1].apply(x, sigma, kind, half_lens, boundary)
 
 
 # ------------------------------------------------------------------ batch
@@ -716,5 +821,5 @@ def scale_of(sigma: float) -> float:
 __all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "iir_laplacian", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
            "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of",
            "Batch", "autotune_batch", "row_chunk_choices", "Frame", "blur_iir_adjoint", "laplacian_adjoint",
-           "plane_dots", "dblur_dsigma_parts", "iir_laplacian_grad", "iir_hessian"]
+           "plane_dots", "dblur_dsigma_parts", "iir_laplacian_grad", "fir_laplacian_grad", "iir_hessian"]
 _ = math

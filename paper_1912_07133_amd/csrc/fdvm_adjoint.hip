@@ -265,6 +265,46 @@ hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, f
     return hipGetLastError();
 }
 
+namespace {
+struct FirTail {
+    int K;
+    float h[FDVM_MAX_FIR_HALF + 1];
+};
+
+// tab[m] = sum_{k = m+1..K} h(k), m = 0..K-1: the tap mass of the FIR that
+// lies beyond lag m, each entry summed on its own in a fixed order
+__global__ __launch_bounds__(256) void fir_tail_kernel(FirTail ft, double *__restrict__ tab) {
+    for (int m = blockIdx.x * 256 + threadIdx.x; m < ft.K; m += gridDim.x * 256) {
+        double t = 0.0;
+        for (int k = ft.K; k > m; --k) t += (double)ft.h[k];
+        tab[m] = t;
+    }
+}
+}  // namespace
+
+hipError_t launch_fir_tail_table(const double *h, int K, double *tab, hipStream_t st) {
+    if (K < 1 || K > FDVM_MAX_FIR_HALF) return hipErrorInvalidValue;
+    FirTail ft;
+    ft.K = K;
+    for (int m = 0; m <= K; ++m) ft.h[m] = (float)h[m];
+    hipLaunchKernelGGL(fir_tail_kernel, dim3((unsigned)((K + 255) / 256)), dim3(256), 0, st, ft, tab);
+    return hipGetLastError();
+}
+
+hipError_t launch_fold_fir(const float *src, int64_t src_pitch, float *dst, int64_t dst_pitch, int64_t H, int64_t W,
+                           int K, const double *tab, int axis, hipStream_t st) {
+    FoldArgs a{};
+    a.nscales = 1;
+    a.s[0].mtail = K;   // tab[m] = 0 from m = K on
+    if (axis == 1)
+        hipLaunchKernelGGL(fold_cols_kernel, dim3((unsigned)((W + 63) / 64), 1u), dim3(64 * FOLD_WAVES), 0, st, src,
+                           src_pitch, (int64_t)0, dst, dst_pitch, (int64_t)0, (int)H, (int)W, a, tab, (int64_t)0);
+    else
+        hipLaunchKernelGGL(fold_rows_kernel, dim3((unsigned)((H + 3) / 4), 1u), dim3(256), 0, st, src, src_pitch,
+                           (int64_t)0, dst, dst_pitch, (int64_t)0, (int)H, (int)W, a, tab, (int64_t)0);
+    return hipGetLastError();
+}
+
 hipError_t launch_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane, int nscales,
                                     const double *sigmas, float *out, int64_t out_pitch, int64_t out_plane,
                                     hipStream_t st) {

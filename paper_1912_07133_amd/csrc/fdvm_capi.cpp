@@ -115,7 +115,8 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
         *out = f;
         return FDVM_OK;
     }
-    if (kind == FDVM_FIR_COLORED_SG || kind == FDVM_FIR_GAUSSIAN) {
+    if (kind == FDVM_FIR_COLORED_SG || kind == FDVM_FIR_GAUSSIAN || kind == FDVM_FIR_COLORED_SG_DSIGMA ||
+        kind == FDVM_FIR_GAUSSIAN_DSIGMA) {
         if (!(sigma >= 0.25 && sigma <= 1024.0)) return FDVM_ERANGE;
         const int K = fir_half_len > 0 ? fir_half_len : (int)std::ceil(3.0 * sigma - 1e-9);
         if (K < 1 || K > FDVM_MAX_FIR_HALF) return FDVM_ERANGE;
@@ -124,12 +125,13 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
         f.order = K;
         f.ntaps = 2 * K + 1;
         int rc;
-        if (kind == FDVM_FIR_COLORED_SG) {
+        if (kind == FDVM_FIR_COLORED_SG || kind == FDVM_FIR_COLORED_SG_DSIGMA) {
             f.omega_c = 3.0 / sigma;
             if (!(f.omega_c < 3.141592653589793)) return FDVM_ERANGE;
-            rc = colored_sg_taps(sigma, K, f.omega_c, taps);
+            rc = kind == FDVM_FIR_COLORED_SG ? colored_sg_taps(sigma, K, f.omega_c, taps)
+                                             : colored_sg_dtaps(sigma, K, f.omega_c, taps);
         } else {
-            rc = gaussian_taps(sigma, K, taps);
+            rc = kind == FDVM_FIR_GAUSSIAN ? gaussian_taps(sigma, K, taps) : gaussian_dtaps(sigma, K, taps);
         }
         if (rc != 0) return FDVM_ERANGE;
         f.b0 = taps[K];
@@ -138,6 +140,30 @@ fdvm_status fdvm_filter_design(fdvm_kind kind, int order, double sigma, int fir_
     }
     return FDVM_EINVAL;
 }
+
+namespace {
+size_t plane_bytes(int64_t H, int64_t W, int n) { return ((size_t)H * W * sizeof(float) * n + 255) & ~(size_t)255; }
+
+// IIR backward: gB | P1 | P2 (nscales planes each) | inner | 3 nscales doubles.
+// inner: column states + tail table (blur adjoint, P2 as its u planes) or
+// column states of the derivative passes, or the inner-product partials.
+size_t iir_backward_inner_bytes(int64_t H, int64_t W, int nscales) {
+    const size_t a = iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS) + fold_workspace_bytes(H, W, nscales);
+    const size_t b = dots_workspace_bytes(H, nscales);
+    return a > b ? a : b;
+}
+size_t iir_backward_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    return 3 * plane_bytes(H, W, nscales) + iir_backward_inner_bytes(H, W, nscales) +
+           (((size_t)3 * nscales * sizeof(double) + 255) & ~(size_t)255);
+}
+// FIR backward: gB (nscales planes) | three single planes | tail table |
+// inner-product partials | 2 nscales doubles
+size_t fir_backward_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    return plane_bytes(H, W, nscales) + 3 * plane_bytes(H, W, 1) +
+           ((((size_t)std::max(H, W)) * sizeof(double) + 255) & ~(size_t)255) + dots_workspace_bytes(H, nscales) +
+           (((size_t)2 * nscales * sizeof(double) + 255) & ~(size_t)255);
+}
+}  // namespace
 
 size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len) {
     if (H < 1 || W < 1 || nscales < 1) return 0;
@@ -153,6 +179,8 @@ size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_h
                    iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS) + fold_workspace_bytes(H, W, nscales);
         case FDVM_OP_PLANE_DOTS: return dots_workspace_bytes(H, nscales);
         case FDVM_OP_FIR_LAPLACIAN: return fir_laplacian_workspace_bytes(H, W);
+        case FDVM_OP_IIR_LAPLACIAN_BACKWARD: return iir_backward_workspace_bytes(H, W, nscales);
+        case FDVM_OP_FIR_LAPLACIAN_BACKWARD: return fir_backward_workspace_bytes(H, W, nscales);
         case FDVM_OP_IIR_HESSIAN:
             return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
                    iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H) +
@@ -333,6 +361,34 @@ fdvm_status fdvm_iir_hessian(const void *in, fdvm_dtype dt, int64_t H, int64_t W
     return from_hip(e);
 }
 
+namespace {
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// G^T = (fold_x + zero-start x pass) (fold_y + zero-start y pass), u: nscales
+// planes of pitch W (G_y^T g), states: column-pass states, tab: the tails
+hipError_t blur_iir_adjoint_core(const float *g, int64_t pitch, int64_t plane_stride, int64_t H, int64_t W,
+                                 float *out, int64_t out_pitch, int64_t out_plane_stride, const IirParams &prm,
+                                 fdvm_boundary bc, float *u, void *states, double *tab, hipStream_t hs) {
+    const int nscales = prm.nscales;
+    IirParams zp = prm;
+    zp.boundary = FDVM_BC_ZERO;
+    hipError_t e = launch_iir_cols(g, pitch, plane_stride, nullptr, u, H, W, W, H * W, false, zp, states, hs);
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE) e = launch_fold_table(H, W, prm, tab, hs);
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
+        e = launch_fold(g, pitch, plane_stride, u, W, H * W, H, W, prm, tab, 1, hs);
+    for (int s = 0; e == hipSuccess && s < nscales; ++s) {
+        IirParams one = zp;
+        one.nscales = 1;
+        one.s[0] = zp.s[s];
+        e = launch_iir_rows(u + (int64_t)s * H * W, FDVM_F32, H, W, W, out + (int64_t)s * out_plane_stride, out_pitch,
+                            out_plane_stride, nullptr, 0, one, hs);
+    }
+    if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
+        e = launch_fold(u, W, H * W, out, out_pitch, out_plane_stride, H, W, prm, tab, 0, hs);
+    return e;
+}
+}  // namespace
+
 fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                                   float *out, int64_t out_pitch, int64_t out_plane_stride,
                                   const fdvm_filter *filters, int nscales, fdvm_boundary bc, void *ws,
@@ -348,32 +404,16 @@ fdvm_status fdvm_blur_iir_adjoint(const float *g, int64_t H, int64_t W, int64_t 
     if (st != FDVM_OK) return st;
     if (prm.order == CPAIR) return FDVM_EUNSUPPORTED;   // folded tails are built for real-pole sections
     if (!ws) return FDVM_EINVAL;
-    const size_t ubytes = ((size_t)H * W * sizeof(float) * nscales + 255) & ~(size_t)255;
+    const size_t ubytes = align256((size_t)H * W * sizeof(float) * nscales);
     const size_t sbytes = iir_cols_workspace_bytes(H, W, nscales, prm.order);
     if (ws_bytes < ubytes + sbytes + fold_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
     if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    // G^T = (fold_x + zero-start x pass) (fold_y + zero-start y pass)
     // ws: G_y^T g (pitch W) | column states | tail table T_s(m)
-    IirParams zp = prm;
-    zp.boundary = FDVM_BC_ZERO;
     float *u = static_cast<float *>(ws);
     void *states = static_cast<char *>(ws) + ubytes;
     double *tab = reinterpret_cast<double *>(static_cast<char *>(ws) + ubytes + sbytes);
-    hipError_t e = launch_iir_cols(g, pitch, plane_stride, nullptr, u, H, W, W, H * W, false, zp, states, hs);
-    if (e == hipSuccess && bc == FDVM_BC_REPLICATE) e = launch_fold_table(H, W, prm, tab, hs);
-    if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
-        e = launch_fold(g, pitch, plane_stride, u, W, H * W, H, W, prm, tab, 1, hs);
-    for (int s = 0; e == hipSuccess && s < nscales; ++s) {
-        IirParams one = zp;
-        one.nscales = 1;
-        one.s[0] = zp.s[s];
-        e = launch_iir_rows(u + (int64_t)s * H * W, FDVM_F32, H, W, W, out + (int64_t)s * out_plane_stride, out_pitch,
-                            out_plane_stride, nullptr, 0, one, hs);
-    }
-    if (e == hipSuccess && bc == FDVM_BC_REPLICATE)
-        e = launch_fold(u, W, H * W, out, out_pitch, out_plane_stride, H, W, prm, tab, 0, hs);
-    return from_hip(e);
+    return from_hip(blur_iir_adjoint_core(g, pitch, plane_stride, H, W, out, out_pitch, out_plane_stride, prm, bc, u,
+                                          states, tab, static_cast<hipStream_t>(stream)));
 }
 
 fdvm_status fdvm_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
@@ -628,3 +668,175 @@ fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_
 }
 
 }  // extern "C"
+
+namespace {
+// shared argument checks of the two backward calls
+fdvm_status backward_check(const void *x, fdvm_dtype dt, int64_t H, int64_t W, int64_t x_pitch,
+                           int64_t x_frame_stride, const float *V, const float *gV, int64_t pitch,
+                           int64_t plane_stride, int64_t v_frame_stride, int nframes, int nscales, fdvm_boundary bc,
+                           unsigned what, const float *gx, int64_t gx_pitch, int64_t gx_frame_stride,
+                           const double *gsigma, const void *ws) {
+    if (what == 0 || (what & ~(unsigned)(FDVM_GRAD_X | FDVM_GRAD_SIGMA))) return FDVM_EINVAL;
+    if (nframes < 1 || !ws) return FDVM_EINVAL;
+    if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
+    fdvm_status st = check_planes(gV, H, W, pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (H > 65535 || W > 16384) return FDVM_EINVAL;
+    if (nframes > 1 && v_frame_stride < (int64_t)nscales * std::max(plane_stride, H * pitch)) return FDVM_EINVAL;
+    if (what & FDVM_GRAD_SIGMA) {
+        if (!V || !gsigma) return FDVM_EINVAL;
+        st = check_image(x, H, W, x_pitch);
+        if (st != FDVM_OK) return st;
+        if (check_dtype(dt) != FDVM_OK) return FDVM_EINVAL;
+        if (nframes > 1 && x_frame_stride < H * x_pitch) return FDVM_EINVAL;
+    }
+    if (what & FDVM_GRAD_X) {
+        st = check_image(gx, H, W, gx_pitch);
+        if (st != FDVM_OK) return st;
+        if (nframes > 1 && gx_frame_stride < H * gx_pitch) return FDVM_EINVAL;
+        if (static_cast<const void *>(gx) == static_cast<const void *>(gV)) return FDVM_EINVAL;
+    }
+    return FDVM_OK;
+}
+
+size_t elem_bytes(fdvm_dtype dt) { return dt == FDVM_F32 ? 4 : 2; }
+}  // namespace
+
+extern "C" fdvm_status fdvm_iir_laplacian_backward(const void *x, fdvm_dtype dt, int64_t H, int64_t W,
+                                                   int64_t x_pitch, int64_t x_frame_stride, const float *V,
+                                                   const float *gV, int64_t pitch, int64_t plane_stride,
+                                                   int64_t v_frame_stride, int nframes, const fdvm_filter *filters,
+                                                   int nscales, fdvm_boundary bc, unsigned what, float *gx,
+                                                   int64_t gx_pitch, int64_t gx_frame_stride, double *gsigma,
+                                                   void *ws, size_t ws_bytes, void *stream) {
+    fdvm_status st = backward_check(x, dt, H, W, x_pitch, x_frame_stride, V, gV, pitch, plane_stride, v_frame_stride,
+                                    nframes, nscales, bc, what, gx, gx_pitch, gx_frame_stride, gsigma, ws);
+    if (st != FDVM_OK) return st;
+    IirParams prm, dprm;
+    st = iir_params(filters, nscales, bc, &prm);
+    if (st != FDVM_OK) return st;
+    if (prm.order == CPAIR || filters[0].kind != FDVM_IIR_REPEATED_POLE) return FDVM_EUNSUPPORTED;
+    if (W > 8 * 64 * 32) return FDVM_EUNSUPPORTED;
+    if (ws_bytes < iir_backward_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
+    double sig[FDVM_MAX_SCALES];
+    for (int s = 0; s < nscales; ++s) sig[s] = filters[s].sigma;
+    if (what & FDVM_GRAD_SIGMA) {
+        fdvm_filter df[FDVM_MAX_SCALES];
+        for (int s = 0; s < nscales; ++s) {
+            st = fdvm_filter_design(FDVM_IIR_REPEATED_POLE_DSIGMA, filters[s].order, filters[s].sigma, 0, &df[s],
+                                    nullptr, 0);
+            if (st != FDVM_OK) return st;
+        }
+        st = iir_params(df, nscales, bc, &dprm, true);
+        if (st != FDVM_OK) return st;
+    }
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int64_t P = H * W;   // workspace planes: pitch W, plane H W
+    char *w = static_cast<char *>(ws);
+    float *gB = reinterpret_cast<float *>(w);
+    float *P1 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales));
+    float *P2 = reinterpret_cast<float *>(w + 2 * plane_bytes(H, W, nscales));
+    char *inner = w + 3 * plane_bytes(H, W, nscales);
+    double *res = reinterpret_cast<double *>(inner + iir_backward_inner_bytes(H, W, nscales));
+    const size_t sbytes = iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS);
+    hipError_t e = hipSuccess;
+    for (int f = 0; e == hipSuccess && f < nframes; ++f) {
+        const float *gVf = gV + (int64_t)f * v_frame_stride;
+        e = launch_laplacian_adjoint(gVf, H, W, pitch, plane_stride, nscales, sig, gB, W, P, hs);
+        if (e == hipSuccess && (what & FDVM_GRAD_X)) {
+            e = blur_iir_adjoint_core(gB, W, P, H, W, P1, W, P, prm, bc, P2, inner,
+                                      reinterpret_cast<double *>(inner + sbytes), hs);
+            if (e == hipSuccess)
+                e = launch_sum_planes(P1, W, P, nscales, H, W, gx + (int64_t)f * gx_frame_stride, gx_pitch, hs);
+        }
+        if (e == hipSuccess && (what & FDVM_GRAD_SIGMA)) {
+            const void *xf = static_cast<const char *>(x) + (int64_t)f * x_frame_stride * (int64_t)elem_bytes(dt);
+            // P1 = G_x x, P2 = G'_x x, then in place P2 = G_y G'_x x, P1 = G'_y G_x x
+            e = launch_iir_rows(xf, dt, H, W, x_pitch, P1, W, P, nullptr, 0, prm, hs);
+            if (e == hipSuccess) e = launch_iir_rows(xf, dt, H, W, x_pitch, P2, W, P, nullptr, 0, dprm, hs);
+            if (e == hipSuccess) e = launch_iir_cols(P2, W, P, nullptr, P2, H, W, W, P, false, prm, inner, hs);
+            if (e == hipSuccess) e = launch_iir_cols(P1, W, P, nullptr, P1, H, W, W, P, false, dprm, inner, hs);
+            if (e == hipSuccess)
+                e = launch_plane_dots(gVf, V + (int64_t)f * v_frame_stride, H, W, pitch, plane_stride, nscales, res,
+                                      inner, hs);
+            if (e == hipSuccess) e = launch_plane_dots(gB, P2, H, W, W, P, nscales, res + nscales, inner, hs);
+            if (e == hipSuccess) e = launch_plane_dots(gB, P1, H, W, W, P, nscales, res + 2 * nscales, inner, hs);
+            if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 2, sig, nscales, f > 0, gsigma, hs);
+        }
+    }
+    return from_hip(e);
+}
+
+extern "C" fdvm_status fdvm_fir_laplacian_backward(const void *x, fdvm_dtype dt, int64_t H, int64_t W,
+                                                   int64_t x_pitch, int64_t x_frame_stride, const float *V,
+                                                   const float *gV, int64_t pitch, int64_t plane_stride,
+                                                   int64_t v_frame_stride, int nframes, const double *taps,
+                                                   const double *dtaps, const int32_t *half_len,
+                                                   const int32_t *tap_offset, const double *sigmas, int nscales,
+                                                   fdvm_boundary bc, unsigned what, float *gx, int64_t gx_pitch,
+                                                   int64_t gx_frame_stride, double *gsigma, void *ws,
+                                                   size_t ws_bytes, void *stream) {
+    fdvm_status st = backward_check(x, dt, H, W, x_pitch, x_frame_stride, V, gV, pitch, plane_stride, v_frame_stride,
+                                    nframes, nscales, bc, what, gx, gx_pitch, gx_frame_stride, gsigma, ws);
+    if (st != FDVM_OK) return st;
+    if (!taps || !half_len || !tap_offset || !sigmas) return FDVM_EINVAL;
+    if ((what & FDVM_GRAD_SIGMA) && !dtaps) return FDVM_EINVAL;
+    for (int s = 0; s < nscales; ++s) {
+        if (half_len[s] < 1 || half_len[s] > FDVM_MAX_FIR_HALF) return FDVM_ERANGE;
+        if (tap_offset[s] < 0) return FDVM_EINVAL;
+        if (!finite_pos(sigmas[s])) return FDVM_ERANGE;
+        const double *h = taps + tap_offset[s];
+        const int K = half_len[s];
+        for (int m = 1; m <= K; ++m)
+            if (h[K + m] != h[K - m]) return FDVM_EINVAL;   // symmetric taps only
+    }
+    if (ws_bytes < fir_backward_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    const int64_t P = H * W;
+    char *w = static_cast<char *>(ws);
+    float *gB = reinterpret_cast<float *>(w);
+    float *Q0 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales));
+    float *Q1 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales) + plane_bytes(H, W, 1));
+    float *Q2 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales) + 2 * plane_bytes(H, W, 1));
+    char *rest = w + plane_bytes(H, W, nscales) + 3 * plane_bytes(H, W, 1);
+    double *tab = reinterpret_cast<double *>(rest);
+    char *dots = rest + ((((size_t)std::max(H, W)) * sizeof(double) + 255) & ~(size_t)255);
+    double *res = reinterpret_cast<double *>(dots + dots_workspace_bytes(H, nscales));
+    const bool rep = bc == FDVM_BC_REPLICATE;
+    hipError_t e = hipSuccess;
+    for (int f = 0; e == hipSuccess && f < nframes; ++f) {
+        const float *gVf = gV + (int64_t)f * v_frame_stride;
+        e = launch_laplacian_adjoint(gVf, H, W, pitch, plane_stride, nscales, sigmas, gB, W, P, hs);
+        for (int s = 0; e == hipSuccess && s < nscales; ++s) {
+            const int K = half_len[s];
+            const double *h = taps + tap_offset[s] + K;   // h(0..K)
+            const float *g = gB + (int64_t)s * P;
+            if (what & FDVM_GRAD_X) {
+                float *gxf = gx + (int64_t)f * gx_frame_stride;
+                // G^T = (fold_x + zero-extension x pass) (fold_y + zero-extension y pass)
+                e = launch_fir_pass(g, FDVM_F32, H, W, W, Q0, W, 1, FDVM_BC_ZERO, h, K, false, hs);
+                if (e == hipSuccess && rep) e = launch_fir_tail_table(h, K, tab, hs);
+                if (e == hipSuccess && rep) e = launch_fold_fir(g, W, Q0, W, H, W, K, tab, 1, hs);
+                if (e == hipSuccess)
+                    e = launch_fir_pass(Q0, FDVM_F32, H, W, W, gxf, gx_pitch, 0, FDVM_BC_ZERO, h, K, s > 0, hs);
+                if (e == hipSuccess && rep) e = launch_fold_fir(Q0, W, gxf, gx_pitch, H, W, K, tab, 0, hs);
+            }
+            if (e == hipSuccess && (what & FDVM_GRAD_SIGMA)) {
+                const void *xf = static_cast<const char *>(x) + (int64_t)f * x_frame_stride * (int64_t)elem_bytes(dt);
+                const double *dh = dtaps + tap_offset[s] + K;
+                // dB/dsigma = G'_y G_x x + G_y G'_x x, then <gB_s, dB_s/dsigma>
+                e = launch_fir_pass(xf, dt, H, W, x_pitch, Q0, W, 0, bc, h, K, false, hs);
+                if (e == hipSuccess) e = launch_fir_pass(xf, dt, H, W, x_pitch, Q1, W, 0, bc, dh, K, false, hs);
+                if (e == hipSuccess) e = launch_fir_pass(Q0, FDVM_F32, H, W, W, Q2, W, 1, bc, dh, K, false, hs);
+                if (e == hipSuccess) e = launch_fir_pass(Q1, FDVM_F32, H, W, W, Q2, W, 1, bc, h, K, true, hs);
+                if (e == hipSuccess) e = launch_plane_dots(g, Q2, H, W, W, P, 1, res + nscales + s, dots, hs);
+            }
+        }
+        if (e == hipSuccess && (what & FDVM_GRAD_SIGMA)) {
+            e = launch_plane_dots(gVf, V + (int64_t)f * v_frame_stride, H, W, pitch, plane_stride, nscales, res, dots,
+                                  hs);
+            if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 1, sigmas, nscales, f > 0, gsigma, hs);
+        }
+    }
+    return from_hip(e);
+}

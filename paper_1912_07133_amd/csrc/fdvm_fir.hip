@@ -62,7 +62,8 @@ __device__ __forceinline__ int lds_pad(int q) { return q + q / FIR_R; }
 template <typename TIn>
 __global__ __launch_bounds__(ROW_BLOCK) void fir_rows_kernel(const TIn *__restrict__ in, int64_t in_pitch,
                                                               float *__restrict__ out, int64_t out_pitch,
-                                                              int H, int W, int boundary, Half hh) {
+                                                              int H, int W, int boundary, int accumulate,
+                                                              Half hh) {
     constexpr int R = FIR_R;
     extern __shared__ float smem[];
     const int K = hh.K;
@@ -114,13 +115,13 @@ __global__ __launch_bounds__(ROW_BLOCK) void fir_rows_kernel(const TIn *__restri
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int col = xb + t * R + j;
-        if (col < W) dst[col] = acc[j];
+        if (col < W) dst[col] = accumulate ? dst[col] + acc[j] : acc[j];
     }
 }
 
 __global__ __launch_bounds__(256) void fir_cols_kernel(const float *__restrict__ in, int64_t in_pitch,
                                                         float *__restrict__ out, int64_t out_pitch, int H,
-                                                        int W, int boundary, Half hh) {
+                                                        int W, int boundary, int accumulate, Half hh) {
     constexpr int R = COL_R;
     extern __shared__ float hz[];
     const int K = hh.K;
@@ -167,20 +168,32 @@ __global__ __launch_bounds__(256) void fir_cols_kernel(const float *__restrict__
     if (col < W) {
 #pragma unroll
         for (int j = 0; j < R; ++j)
-            if (y0 + j < H) out[(int64_t)(y0 + j) * out_pitch + col] = acc[j];
+            if (y0 + j < H) {
+                float *o = out + (int64_t)(y0 + j) * out_pitch + col;
+                *o = accumulate ? *o + acc[j] : acc[j];
+            }
     }
 }
 
 template <typename T>
 hipError_t rows_t(const void *in, int64_t H, int64_t W, int64_t in_pitch, float *tmp, int64_t tmp_pitch,
-                  int boundary, const Half &hh, hipStream_t st) {
+                  int boundary, const Half &hh, hipStream_t st, int accumulate = 0) {
     const int K = hh.K;
     const int nblk = (2 * K + 2 * FIR_R - 1) / FIR_R;
     const int span = ROW_SPAN + FIR_R * nblk;
     const size_t lds = sizeof(float) * ((2 * K + 4 * FIR_R + 1) + span + span / FIR_R + 1);
     dim3 grid((unsigned)((W + ROW_SPAN - 1) / ROW_SPAN), (unsigned)H);
     hipLaunchKernelGGL(fir_rows_kernel<T>, grid, dim3(ROW_BLOCK), lds, st, static_cast<const T *>(in),
-                       in_pitch, tmp, tmp_pitch, (int)H, (int)W, boundary, hh);
+                       in_pitch, tmp, tmp_pitch, (int)H, (int)W, boundary, accumulate, hh);
+    return hipGetLastError();
+}
+
+hipError_t cols_f(const float *in, int64_t in_pitch, float *out, int64_t out_pitch, int64_t H, int64_t W,
+                  int boundary, const Half &hh, hipStream_t st, int accumulate = 0) {
+    const size_t lds = sizeof(float) * (2 * hh.K + 4 * COL_R + 1);
+    dim3 grid((unsigned)((W + 63) / 64), (unsigned)((H + 4 * COL_R - 1) / (4 * COL_R)));
+    hipLaunchKernelGGL(fir_cols_kernel, grid, dim3(256), lds, st, in, in_pitch, out, out_pitch, (int)H, (int)W,
+                       boundary, accumulate, hh);
     return hipGetLastError();
 }
 
@@ -225,14 +238,31 @@ hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t i
             default: return hipErrorInvalidValue;
         }
         if (e != hipSuccess) return e;
-        const size_t lds = sizeof(float) * (2 * hh.K + 4 * COL_R + 1);
-        dim3 grid((unsigned)((W + 63) / 64), (unsigned)((H + 4 * COL_R - 1) / (4 * COL_R)));
-        hipLaunchKernelGGL(fir_cols_kernel, grid, dim3(256), lds, st, tmp, tmp_pitch, dst, out_pitch, (int)H,
-                           (int)W, boundary, hh);
-        e = hipGetLastError();
+        e = cols_f(tmp, tmp_pitch, dst, out_pitch, H, W, boundary, hh, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+hipError_t launch_fir_pass(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                           int64_t out_pitch, int axis, int boundary, const double *h, int K, bool accumulate,
+                           hipStream_t st) {
+    if (K < 0 || K > MAXK) return hipErrorInvalidValue;
+    Half hh;
+    hh.K = K;
+    for (int m = 0; m <= K; ++m) hh.h[m] = (float)h[m];
+    const int acc = accumulate ? 1 : 0;
+    if (axis == 1) {
+        if (dtype != FDVM_F32) return hipErrorInvalidValue;
+        return cols_f(static_cast<const float *>(in), in_pitch, out, out_pitch, H, W, boundary, hh, st, acc);
+    }
+    switch (dtype) {
+        case FDVM_U16: return rows_t<uint16_t>(in, H, W, in_pitch, out, out_pitch, boundary, hh, st, acc);
+        case FDVM_F32: return rows_t<float>(in, H, W, in_pitch, out, out_pitch, boundary, hh, st, acc);
+        case FDVM_F16: return rows_t<_Float16>(in, H, W, in_pitch, out, out_pitch, boundary, hh, st, acc);
+        case FDVM_BF16: return rows_t<bf16_t>(in, H, W, in_pitch, out, out_pitch, boundary, hh, st, acc);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace fdvm

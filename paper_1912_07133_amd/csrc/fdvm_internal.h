@@ -50,6 +50,9 @@ Cascade sigma_derivative_realisation(int K, double sigma);
 // Coloured Savitzky-Golay / Gaussian FIR designs (float64, h(-K..K)).
 int colored_sg_taps(double sigma, int K, double omega_c, double *taps);
 int gaussian_taps(double sigma, int K, double *taps);
+// d h / d sigma of those two designs at fixed K
+int colored_sg_dtaps(double sigma, int K, double omega_c, double *dtaps);
+int gaussian_dtaps(double sigma, int K, double *dtaps);
 
 // ---------------------------------------------------------------- kernels
 struct IirScaleParams {
@@ -124,6 +127,19 @@ hipError_t launch_fold_table(int64_t H, int64_t W, const IirParams &prm, double 
 hipError_t launch_fold(const float *src, int64_t src_pitch, int64_t src_plane, float *dst, int64_t dst_pitch,
                        int64_t dst_plane, int64_t H, int64_t W, const IirParams &prm, const double *tab, int axis,
                        hipStream_t st);
+// FIR fold (transpose of the replicate extension): tab[m] = sum_{k>m} h(k)
+// for m < K (h = h(0..K) as float32, summed in float64), then the fold of
+// launch_fold along y (axis 1) or x (axis 0) for one plane.
+hipError_t launch_fir_tail_table(const double *h, int K, double *tab, hipStream_t st);
+hipError_t launch_fold_fir(const float *src, int64_t src_pitch, float *dst, int64_t dst_pitch, int64_t H, int64_t W,
+                           int K, const double *tab, int axis, hipStream_t st);
+// out = sum_s in_s (float32, scale order); in: nscales planes
+hipError_t launch_sum_planes(const float *in, int64_t pitch, int64_t plane, int nscales, int64_t H, int64_t W,
+                             float *out, int64_t out_pitch, hipStream_t st);
+// gsigma[s] (+)= 2/sigma_s vv[s] + sum_{t < nterms} terms[t nscales + s]
+// (device float64 arrays; sigmas on the host)
+hipError_t launch_gsigma(const double *vv, const double *terms, int nterms, const double *sigmas, int nscales,
+                         bool accumulate, double *gsigma, hipStream_t st);
 hipError_t launch_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane, int nscales,
                                     const double *sigmas, float *out, int64_t out_pitch, int64_t out_plane,
                                     hipStream_t st);
@@ -158,6 +174,12 @@ hipError_t launch_fir_mfma_half(const void *in, int dtype, int64_t H, int64_t W,
                                 const int32_t *half_len, const int32_t *tap_offset, int nscales, int boundary,
                                 hipStream_t stream);
 size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half);
+// One direct FIR pass along x (axis 0, frame of any input type) or y (axis 1,
+// float32 input): out (+)= sum_m h(|m|) in_ext(n - m), h = h(0..K) (float64,
+// used as float32), boundary FDVM_BC_REPLICATE or FDVM_BC_ZERO.
+hipError_t launch_fir_pass(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, float *out,
+                           int64_t out_pitch, int axis, int boundary, const double *h, int K, bool accumulate,
+                           hipStream_t st);
 hipError_t launch_fir(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch,
                       float *out, int64_t out_pitch, int64_t plane_stride,
                       const double *taps, const int32_t *half_len, const int32_t *tap_offset,
