@@ -56,7 +56,6 @@ constexpr int HT_WPOS = HT_WPB / HT_WROW;   // and two side by side along the ro
 // the 32 rows one instruction touches fall on few memory channels
 constexpr int HT_PAD = 8;
 constexpr int HT_G = 16;          // samples per instruction
-constexpr int HT_NR = 4;          // ring slots: sample loads run HT_NR - 1 groups ahead
 constexpr int HT_ARG_TAPS = 880;  // tap words that fit in the kernel arguments
 constexpr int HT_KP_MAX = ((FDVM_MAX_FIR_HALF + 31) / 32) * 32;
 constexpr int HT_NE_MAX = 2 * HT_KP_MAX + 120;
@@ -169,10 +168,13 @@ template <typename H, int SRC, bool OUT_F32, bool FAST>
 __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     const uint16_t *__restrict__ src, const uint16_t *__restrict__ src_lo, int64_t src_pitch, int64_t src_plane,
     int R, int n, int n_in, void *__restrict__ dst, uint16_t *__restrict__ dst_lo, int64_t dst_pitch,
-    int64_t dst_plane, int R_out, int boundary, int vec_out, const u32x4 *__restrict__ tables, HalfSet hs) {
+    int64_t dst_plane, int R_out, int boundary, int vec_out, const u32x4 *__restrict__ tables, HalfSet hs,
+    int stage_off) {
     constexpr bool SPLIT = SRC != SRC_HALF;   // A carries a lo' part
     constexpr bool PAIR = SRC == SRC_PAIR;
-    extern __shared__ u32x4 lds[];            // the scale's table: NE hi entries, NE lo' entries
+    // the scale's table (NE hi entries, NE lo' entries), then (FAST) each
+    // wavefront's staging buffer from entry stage_off on
+    extern __shared__ u32x4 lds[];
     const int nrt = (R_out + HT_ROWS * HT_WROW - 1) / (HT_ROWS * HT_WROW);
     const int npg = (n + HT_POS * HT_WPOS - 1) / (HT_POS * HT_WPOS);
     const int S = hs.nscales;
@@ -202,27 +204,6 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     const uint16_t *rh = src + roff;
     const uint16_t *rl = PAIR ? src_lo + roff : nullptr;
     const int cb = p0 - KP + 8 * g8;   // first sample of this lane's eight in group 0
-    auto load = [&](int g, u32x4 &vh, u32x4 &vl) {
-        const int c0 = cb + HT_G * g;
-        if constexpr (FAST) {
-            const int cl = min(max(c0, 0), n_in - 8);
-            vh = *reinterpret_cast<const u32x4 *>(rh + cl);
-            if constexpr (PAIR) vl = *reinterpret_cast<const u32x4 *>(rl + cl);
-        } else {
-            uint32_t eh[8], el[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int cc = min(max(c0 + u, 0), n_in - 1);
-                eh[u] = rh[cc];
-                if constexpr (PAIR) el[u] = rl[cc];
-            }
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                vh[w] = eh[2 * w] | (eh[2 * w + 1] << 16);
-                if constexpr (PAIR) vl[w] = el[2 * w] | (el[2 * w + 1] << 16);
-            }
-        }
-    };
     // the extension at samples outside [0, n_in): the clamped loads already
     // replicate in the element form; FAST chunks wholly outside take the
     // first / last sample of the clamped chunk, or zero
@@ -265,29 +246,17 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
         l0[e] = 0.0f;
         l1[e] = 0.0f;
     }
-    // rings: samples of group g in slot g % HT_NR (loaded HT_NR - 1 groups
-    // ahead), block 0's tap fragment of group g in slot g % HT_NR (block 1
-    // uses it two groups later)
-    u32x4 ra[HT_NR], rla[HT_NR], bh[HT_NR], bl[HT_NR];
-#pragma unroll
-    for (int q = 0; q < HT_NR - 1; ++q) load(q, ra[q], rla[q]);
+    // block 0's tap fragment of group g in slot g % 4 (block 1 uses it two
+    // groups later)
+    u32x4 bh[4], bl[4];
     const int ebase = C0 + KP + i - 8 * g8;   // block 0's entry at group 0
-    auto step = [&](int g, auto slot_c, auto blocks_c, auto load_c) {
+    // the products of group g from its raw samples vh (and vl)
+    auto mma = [&](int g, u32x4 vh, u32x4 vl, auto slot_c, auto blocks_c) {
         constexpr int k = decltype(slot_c)::value;
         constexpr int BL = decltype(blocks_c)::value;   // 1: block 0, 2: block 1, 3: both
-        if constexpr (decltype(load_c)::value) {
-            constexpr int kn = (k + HT_NR - 1) % HT_NR;
-            load(min(g + HT_NR - 1, NG - 1), ra[kn], rla[kn]);
-        }
-        // keep the loads in this step: the scheduler would otherwise sink
-        // them next to their use three groups later
-        __builtin_amdgcn_sched_barrier(0);
-        u32x4 vh = ra[k], vl, ah, al;
+        u32x4 ah, al;
         extend(g, vh);
-        if constexpr (PAIR) {
-            vl = rla[k];
-            extend(g, vl);
-        }
+        if constexpr (PAIR) extend(g, vl);
         if constexpr (SRC == SRC_U16) {
             split_u16(vh, ah, al);
         } else {
@@ -302,7 +271,7 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
             if constexpr (SPLIT) l0 = Op<H>::mfma(al, bh[k], l0);
         }
         if constexpr (BL & 2) {
-            constexpr int q = (k + HT_NR - 2) % HT_NR;
+            constexpr int q = (k + 2) % 4;
             m1 = Op<H>::mfma(ah, bh[q], m1);
             l1 = Op<H>::mfma(ah, bl[q], l1);
             if constexpr (SPLIT) l1 = Op<H>::mfma(al, bh[q], l1);
@@ -312,21 +281,108 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     using I1 = std::integral_constant<int, 1>;
     using I2 = std::integral_constant<int, 2>;
     using I3 = std::integral_constant<int, 3>;
-    using LOAD = std::true_type;
-    using NOLOAD = std::false_type;
-    static_assert(HT_NR == 4, "phase slots below assume four ring slots");
     // block 0 alone for groups 0, 1; both for 2 .. NG - 3 (K'/8 groups, a
     // multiple of 4); block 1 alone for NG - 2, NG - 1
-    step(0, I{}, I1{}, LOAD{});
-    step(1, I1{}, I1{}, LOAD{});
-    for (int g = 2; g < NG - 2; g += 4) {
-        step(g, I2{}, I3{}, LOAD{});
-        step(g + 1, I3{}, I3{}, LOAD{});
-        step(g + 2, I{}, I3{}, LOAD{});
-        step(g + 3, I1{}, I3{}, LOAD{});
+    if constexpr (FAST) {
+        // Chunks of four groups (64 samples of the wavefront's 32 rows, 4 KB
+        // per plane) are fetched one chunk ahead into registers with whole-
+        // line loads (lane l: row 8 j + l / 8, 16-byte segment l % 8; every
+        // instruction reads 8 full 128-byte lines), then written to this
+        // wavefront's LDS buffer with the segment of row r at slot
+        // segment ^ (r % 8), so that the A fragments (lane i + 32 g: row i,
+        // segment 2 (g % 4) + g) come back conflict-free.  The buffer is the
+        // wavefront's own and LDS operations of a wavefront complete in order,
+        // so no barrier is needed between a chunk's reads and the next write.
+        u32x4 *sh = lds + stage_off + wv * (PAIR ? 512 : 256);
+        u32x4 *sl = sh + 256;
+        const int NC = NG / 4;   // >= 2 (K' >= 32)
+        const int lr = lane >> 3, lq = lane & 7;
+        int64_t roffs[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            roffs[j] = (int64_t)s * src_plane + (int64_t)min(y0 + 8 * j + lr, R - 1) * src_pitch;
+        u32x4 fh[4], fl[4];
+        auto gload = [&](int c) {
+            const int c0 = p0 - KP + 64 * c + 8 * lq;
+            const int cl = min(max(c0, 0), n_in - 8);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                fh[j] = *reinterpret_cast<const u32x4 *>(src + roffs[j] + cl);
+                if constexpr (PAIR) fl[j] = *reinterpret_cast<const u32x4 *>(src_lo + roffs[j] + cl);
+            }
+        };
+        const int rsw = i & 7;
+        auto chunk = [&](int c, auto kind_c) {
+            constexpr int KIND = decltype(kind_c)::value;   // 0 first, 1 middle, 2 last
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                sh[(8 * j + lr) * 8 + (lq ^ lr)] = fh[j];
+                if constexpr (PAIR) sl[(8 * j + lr) * 8 + (lq ^ lr)] = fl[j];
+            }
+            gload(min(c + 1, NC - 1));
+            // keep the refill here: the scheduler would otherwise sink it
+            __builtin_amdgcn_sched_barrier(0);
+            auto grp = [&](auto gi_c, auto blocks_c) {
+                constexpr int gi = decltype(gi_c)::value;
+                const int seg = 2 * gi + g8;
+                const u32x4 vh = sh[i * 8 + (seg ^ rsw)];
+                u32x4 vl;
+                if constexpr (PAIR) vl = sl[i * 8 + (seg ^ rsw)];
+                mma(4 * c + gi, vh, vl, gi_c, blocks_c);
+            };
+            using B0 = std::integral_constant<int, KIND == 0 ? 1 : 3>;
+            using B1 = std::integral_constant<int, KIND == 2 ? 2 : 3>;
+            grp(I{}, B0{});
+            grp(I1{}, B0{});
+            grp(I2{}, B1{});
+            grp(I3{}, B1{});
+        };
+        gload(0);
+        chunk(0, std::integral_constant<int, 0>{});
+        for (int c = 1; c < NC - 1; ++c) chunk(c, std::integral_constant<int, 1>{});
+        chunk(NC - 1, std::integral_constant<int, 2>{});
+    } else {
+        // element loads into a 4-slot register ring, three groups ahead
+        auto load = [&](int g, u32x4 &vh, u32x4 &vl) {
+            const int c0 = cb + HT_G * g;
+            uint32_t eh[8], el[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int cc = min(max(c0 + u, 0), n_in - 1);
+                eh[u] = rh[cc];
+                if constexpr (PAIR) el[u] = rl[cc];
+            }
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                vh[w] = eh[2 * w] | (eh[2 * w + 1] << 16);
+                if constexpr (PAIR) vl[w] = el[2 * w] | (el[2 * w + 1] << 16);
+            }
+        };
+        u32x4 ra[4], rla[4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) load(q, ra[q], rla[q]);
+        auto step = [&](int g, auto slot_c, auto blocks_c, auto load_c) {
+            constexpr int k = decltype(slot_c)::value;
+            if constexpr (decltype(load_c)::value) {
+                constexpr int kn = (k + 3) % 4;
+                load(min(g + 3, NG - 1), ra[kn], rla[kn]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            mma(g, ra[k], rla[k], slot_c, blocks_c);
+        };
+        using LOAD = std::true_type;
+        using NOLOAD = std::false_type;
+        step(0, I{}, I1{}, LOAD{});
+        step(1, I1{}, I1{}, LOAD{});
+        for (int g = 2; g < NG - 2; g += 4) {
+            step(g, I2{}, I3{}, LOAD{});
+            step(g + 1, I3{}, I3{}, LOAD{});
+            step(g + 2, I{}, I3{}, LOAD{});
+            step(g + 3, I1{}, I3{}, LOAD{});
+        }
+        step(NG - 2, I2{}, I2{}, NOLOAD{});
+        step(NG - 1, I3{}, I2{}, NOLOAD{});
     }
-    step(NG - 2, I2{}, I2{}, NOLOAD{});
-    step(NG - 1, I3{}, I2{}, NOLOAD{});
     // D[i][j] of block t sits in lane j + 32 ((i / 4) % 2), register
     // (i / 8) 4 + i % 4: each lane holds rows y0 + 8 q + 4 g8 + (0..3) of
     // output p0 + 32 t + (lane & 31)
@@ -388,12 +444,14 @@ hipError_t rows_pass(const void *src, const void *src_lo, int64_t src_pitch, int
                      hipStream_t st) {
     const unsigned nrt = (unsigned)((R_out + HT_ROWS * HT_WROW - 1) / (HT_ROWS * HT_WROW));
     const unsigned npg = (unsigned)((n + HT_POS * HT_WPOS - 1) / (HT_POS * HT_WPOS));
-    const size_t lds = sizeof(u32x4) * 2 * (size_t)table_entries(kp_max);
+    const int stage_off = 2 * table_entries(kp_max);
+    const int stage = FAST ? HT_WPB * (SRC == SRC_PAIR ? 512 : 256) : 0;   // 16-byte entries
+    const size_t lds = sizeof(u32x4) * (size_t)(stage_off + stage);
     hipLaunchKernelGGL((fir_half_rows_kernel<H, SRC, OUT_F32, FAST>), dim3(nrt * npg * (unsigned)hs.nscales),
                        dim3(HT_WPB * 64), lds, st, static_cast<const uint16_t *>(src),
                        static_cast<const uint16_t *>(src_lo), src_pitch, src_plane, (int)R, (int)n, (int)n_in, dst,
                        static_cast<uint16_t *>(dst_lo), dst_pitch, dst_plane, (int)R_out, boundary, (int)vec_out,
-                       tables, hs);
+                       tables, hs, stage_off);
     return hipGetLastError();
 }
 
