@@ -296,16 +296,19 @@ def run_precision_leg(P, syn, torch, np, dev, stream, log):
 def half_mfma_flops(H, W, Ks, first_pass_products=2):
     """Matrix-core flops the half-operand Toeplitz FIR issues for one H x W
     frame: per pass and scale, one wavefront per 32 rows x 64 outputs along
-    the rows runs 2 K'/16 + 4 groups of 16 samples (K' = K rounded up to 16),
+    the rows runs 2 K'/16 + 4 groups of 16 samples (K' = K rounded up to 32),
     each meeting one 32 x 32 output block in the first and last two groups and
     both otherwise, with 2 products per block in the first pass (hi and lo
     taps; 3 for uint16 frames, whose samples are split too) and 3 in the
-    second (the split intermediate); 32 * 32 * 16 * 2 flops each."""
+    second (the split intermediate); 32 * 32 * 16 * 2 flops each.  The first
+    pass covers the intermediate's padded rows: H rounded up to an odd number
+    of 64-sample lines."""
     total = 0
+    hp = 64 * ((-(-H // 64)) | 1)
     for K in Ks:
-        kp = -(-K // 16) * 16
+        kp = -(-K // 32) * 32
         blocks = 2 * (2 * kp // 16 + 4) - 4
-        for (rows, n), prods in (((H, W), first_pass_products), ((W, H), 3)):
+        for (rows, n), prods in (((hp, W), first_pass_products), ((W, H), 3)):
             waves = -(-rows // 32) * -(-n // 64)
             total += waves * blocks * prods * 32 * 32 * 16 * 2
     return total

@@ -52,10 +52,12 @@ constexpr int HT_WPB = 4;         // wavefronts per work-group
 // samples (128 bytes) of each transposed intermediate row, whole cache lines
 constexpr int HT_WROW = 2;
 constexpr int HT_WPOS = HT_WPB / HT_WROW;   // and two side by side along the rows
-// samples added to the intermediate's row pitch: with a power-of-two pitch
-// the 32 rows one instruction touches fall on few memory channels
-constexpr int HT_PAD = 8;
 constexpr int HT_G = 16;          // samples per instruction
+// row tiles taken together in the launch order (scale, then HT_RG row tiles,
+// then position groups): the work-groups running at once write runs twice as
+// long in each output row, and neighbours along the rows still share their
+// input windows in L2 (1, 2, 4, 8 measured: 2 is best for both passes)
+constexpr int HT_RG = 2;
 constexpr int HT_ARG_TAPS = 880;  // tap words that fit in the kernel arguments
 constexpr int HT_KP_MAX = ((FDVM_MAX_FIR_HALF + 31) / 32) * 32;
 constexpr int HT_NE_MAX = 2 * HT_KP_MAX + 120;
@@ -163,7 +165,8 @@ __global__ __launch_bounds__(256) void fir_half_tables_kernel(u32x4 *__restrict_
 // multiple of 8, rows 16-byte aligned): one clamped 16-byte load and a
 // select; otherwise eight clamped element loads.  Neither form branches
 // around a load, so the loads of later groups stay in flight.  Logical blocks
-// (scale, position group, row tile), scale fastest, XCD-contiguous.
+// (scale, row tile within a group of HT_RG, position group, row-tile group),
+// scale fastest, XCD-contiguous.
 template <typename H, int SRC, bool OUT_F32, bool FAST>
 __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     const uint16_t *__restrict__ src, const uint16_t *__restrict__ src_lo, int64_t src_pitch, int64_t src_plane,
@@ -180,8 +183,11 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     const int S = hs.nscales;
     const int lb = xcd_logical(blockIdx.x, nrt * npg * S);
     const int s = lb % S;
-    const int pg = (lb / S) % npg;
-    const int rt = lb / (S * npg);
+    const int r2 = lb / S;
+    const int rq = r2 / (HT_RG * npg), rw = r2 % (HT_RG * npg);
+    const int rgn = min(HT_RG, nrt - rq * HT_RG);   // row tiles in this group
+    const int rt = rq * HT_RG + rw % rgn;
+    const int pg = rw / rgn;
     const int KP = round_kp(hs.K[s]);
     const int NE = table_entries(KP);
     const int NG = KP / 8 + 4;   // groups: 2 K'/16 + 4
@@ -301,8 +307,13 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
 #pragma unroll
         for (int j = 0; j < 4; ++j)
             roffs[j] = (int64_t)s * src_plane + (int64_t)min(y0 + 8 * j + lr, R - 1) * src_pitch;
-        u32x4 fh[4], fl[4];
-        auto gload = [&](int c) {
+        // AHEAD chunks in flight: chunk c in slot c % AHEAD, refilled with
+        // chunk c + AHEAD once written to LDS (the last chunk again at the
+        // end: an L1 hit).  Two for pair sources; one for the first pass,
+        // whose register budget would otherwise cost a wavefront per SIMD
+        constexpr int AHEAD = PAIR ? 2 : 1;
+        u32x4 fa[4], fla[4], fb[4], flb[4];
+        auto gload = [&](int c, u32x4(&fh)[4], u32x4(&fl)[4]) {
             const int c0 = p0 - KP + 64 * c + 8 * lq;
             const int cl = min(max(c0, 0), n_in - 8);
 #pragma unroll
@@ -312,14 +323,14 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
             }
         };
         const int rsw = i & 7;
-        auto chunk = [&](int c, auto kind_c) {
+        auto chunk = [&](int c, auto kind_c, u32x4(&fh)[4], u32x4(&fl)[4]) {
             constexpr int KIND = decltype(kind_c)::value;   // 0 first, 1 middle, 2 last
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 sh[(8 * j + lr) * 8 + (lq ^ lr)] = fh[j];
                 if constexpr (PAIR) sl[(8 * j + lr) * 8 + (lq ^ lr)] = fl[j];
             }
-            gload(min(c + 1, NC - 1));
+            gload(min(c + AHEAD, NC - 1), fh, fl);
             // keep the refill here: the scheduler would otherwise sink it
             __builtin_amdgcn_sched_barrier(0);
             auto grp = [&](auto gi_c, auto blocks_c) {
@@ -337,10 +348,25 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
             grp(I2{}, B1{});
             grp(I3{}, B1{});
         };
-        gload(0);
-        chunk(0, std::integral_constant<int, 0>{});
-        for (int c = 1; c < NC - 1; ++c) chunk(c, std::integral_constant<int, 1>{});
-        chunk(NC - 1, std::integral_constant<int, 2>{});
+        using FIRST = std::integral_constant<int, 0>;
+        using MID = std::integral_constant<int, 1>;
+        using LAST = std::integral_constant<int, 2>;
+        gload(0, fa, fla);
+        if constexpr (AHEAD == 2) {
+            gload(1, fb, flb);
+            chunk(0, FIRST{}, fa, fla);
+            int c = 1;
+            for (; c + 2 < NC; c += 2) {
+                chunk(c, MID{}, fb, flb);
+                chunk(c + 1, MID{}, fa, fla);
+            }
+            if (c < NC - 1) chunk(c, MID{}, fb, flb);
+            // both slots hold the last chunk by now (the refills are clamped to it)
+        } else {
+            chunk(0, FIRST{}, fa, fla);
+            for (int c = 1; c < NC - 1; ++c) chunk(c, MID{}, fa, fla);
+        }
+        chunk(NC - 1, LAST{}, fa, fla);
     } else {
         // element loads into a 4-slot register ring, three groups ahead
         auto load = [&](int g, u32x4 &vh, u32x4 &vl) {
@@ -388,6 +414,82 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     // output p0 + 32 t + (lane & 31)
     const float post = hs.post[s];
     constexpr float inv_lo = 1.0f / Op<H>::lo_scale;
+    auto value = [&](const floatx16 &m, const floatx16 &l, int q, float (&v)[4]) {
+        const int y = y0 + 8 * q + 4 * g8;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            v[u] = (m[4 * q + u] + l[4 * q + u] * inv_lo) * post;
+            if (!OUT_F32 && !rep && y + u >= R) v[u] = 0.0f;   // zero extension rows
+        }
+    };
+    if constexpr (FAST) {
+        // Each block goes through the wavefront's staging buffer, one 128-byte
+        // LDS row per output: 32 float32 samples (16-byte segment c: rows
+        // y0 + 4 c .. + 3), or the 32 hi samples then the 32 lo' samples
+        // (segment c: rows y0 + 8 (c % 4) .. + 7 of plane c / 4), segment c of
+        // row j at slot c ^ (j % 8) and, for the 8-byte halves the pair form
+        // writes, the half flipped in rows j with j / 8 odd: every group of
+        // lanes that LDS serves together meets distinct banks.  Read back,
+        // lane l holds segment l % 8 of output 8 k + l / 8, so that each store
+        // instruction writes 8 outputs x 128 contiguous bytes (float32) or
+        // 8 x 64 bytes of each plane, not 32 outputs x 32 or 16 bytes.
+        u32x4 *ob = lds + stage_off + wv * (PAIR ? 512 : 256);
+        const int lr = lane >> 3, lq = lane & 7;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const floatx16 &m = t ? m1 : m0;
+            const floatx16 &l = t ? l1 : l0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                float v[4];
+                value(m, l, q, v);
+                if constexpr (OUT_F32) {
+                    ob[i * 8 + ((2 * q + g8) ^ (i & 7))] = __builtin_bit_cast(u32x4, f32x4{v[0], v[1], v[2], v[3]});
+                } else {
+                    uint16_t hi[4], lo[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) split<H>(v[u], hi[u], lo[u]);
+                    u32x2 *ob2 = reinterpret_cast<u32x2 *>(ob);
+                    const int hf = g8 ^ ((i >> 3) & 1);
+                    ob2[2 * (i * 8 + (q ^ (i & 7))) + hf] =
+                        u32x2{(uint32_t)hi[0] | ((uint32_t)hi[1] << 16), (uint32_t)hi[2] | ((uint32_t)hi[3] << 16)};
+                    ob2[2 * (i * 8 + ((4 + q) ^ (i & 7))) + hf] =
+                        u32x2{(uint32_t)lo[0] | ((uint32_t)lo[1] << 16), (uint32_t)lo[2] | ((uint32_t)lo[3] << 16)};
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int j = 8 * k + lr;
+                u32x4 w = ob[j * 8 + (lq ^ lr)];
+                const int p = p0 + 32 * t + j;
+                if (p >= n) continue;
+                const int64_t base = (int64_t)s * dst_plane + (int64_t)p * dst_pitch;
+                if constexpr (OUT_F32) {
+                    const int y = y0 + 4 * lq;
+                    float *o = static_cast<float *>(dst) + base + y;
+                    if (vec_out && y + 3 < R_out) {
+                        *reinterpret_cast<u32x4 *>(o) = w;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (y + u < R_out) o[u] = __uint_as_float(w[u]);
+                    }
+                } else {
+                    if (k & 1) w = u32x4{w[2], w[3], w[0], w[1]};
+                    const int y = y0 + 8 * (lq & 3);
+                    uint16_t *o = (lq < 4 ? static_cast<uint16_t *>(dst) : dst_lo) + base + y;
+                    if (y + 7 < R_out) {
+                        *reinterpret_cast<u32x4 *>(o) = w;
+                    } else {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u)
+                            if (y + u < R_out) o[u] = (uint16_t)(w[u / 2] >> (16 * (u % 2)));
+                    }
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const int p = p0 + 32 * t + i;
@@ -399,11 +501,7 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
         for (int q = 0; q < 4; ++q) {
             const int y = y0 + 8 * q + 4 * g8;
             float v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                v[u] = (m[4 * q + u] + l[4 * q + u] * inv_lo) * post;
-                if (!OUT_F32 && !rep && y + u >= R) v[u] = 0.0f;   // zero extension rows
-            }
+            value(m, l, q, v);
             if constexpr (OUT_F32) {
                 float *o = static_cast<float *>(dst) + base + y;
                 if (vec_out && y + 3 < R_out) {
@@ -456,8 +554,10 @@ hipError_t rows_pass(const void *src, const void *src_lo, int64_t src_pitch, int
 }
 
 // intermediate planes: W rows (one per frame column) of Hp >= H samples,
-// Hp a multiple of 8 so that every row starts 16-byte aligned
-int64_t pair_pitch(int64_t H) { return ((H + 7) & ~(int64_t)7) + HT_PAD; }
+// an odd number of 128-byte lines: every row starts on a line (the staged
+// chunk loads and the output runs then cover whole lines, not two halves),
+// and the rows one instruction touches spread over the memory channels
+int64_t pair_pitch(int64_t H) { return 64 * (((H + 63) / 64) | 1); }
 
 template <typename T, int SRC1>
 hipError_t run_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch, bool vec_in, void *ws, float *out,
