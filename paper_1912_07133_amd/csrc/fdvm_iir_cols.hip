@@ -2,12 +2,18 @@
 // along the row), optionally finished as the scale-normalised Laplacian or the
 // Hessian detector.  Realisation and intermediate formats: fdvm_iir_common.h.
 //
-// Tiles of CT rows:
-//   states  -- every tile's zero-state end states (forward and backward);
-//   scan    -- per column, the states are chained into the true carries that
-//              enter every tile (forward from the top, backward from the bottom);
-//   final   -- every tile independently: backward sweep from its bottom carry,
-//              forward sweep from its top carry, output.  Optionally the
+// Tiles of CT rows, grouped COL_WPB at a time into super tiles:
+//   states  -- every tile's zero-state end states (forward and backward),
+//              combined within its super tile into the states entering each
+//              tile from the super tile's top and bottom edges (zero there),
+//              and into the super tile's own zero-state end states;
+//   scan    -- per column, the super tiles' states are chained into the true
+//              carries that enter every super tile (forward from the top,
+//              backward from the bottom);
+//   final   -- every tile independently: its true carries are the super
+//              tile's carries moved across the rows between them plus the
+//              tile's in-super-tile states; backward sweep from its bottom
+//              carry, forward sweep from its top carry, output.  Optionally the
 //              scale-normalised Laplacian sigma^2 (D20 + D02) is formed here in
 //              float64 from the unrounded blur: y-neighbours come from the
 //              sweep itself (the rows just outside the tile are recovered by
@@ -18,54 +24,112 @@
 namespace fdvm {
 namespace {
 
-// (a) zero-state end states of every CT-row tile (float64).  st layout:
-//     st[((s * nty + ty) * 2K + k) * W + x], k < K forward, k >= K backward.
+// (a) zero-state end states of every CT-row tile (float64), one wavefront per
+//     tile, the COL_WPB tiles of a super tile in one work-group.  Writes, per
+//     tile, the forward state entering it from the top of its super tile and
+//     the backward state entering it from the bottom (both zero at those
+//     edges): lt[((s * nty + ty) * 2K + k) * W + x], k < K forward, k >= K
+//     backward; and per super tile its zero-state end states, laid out the
+//     same way in sst with nsy super tiles.
 template <int K, bool FX>
-__global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m, int H, int W, int nty,
-                                                                      double *__restrict__ st, Args a) {
+__global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m, int H, int W, int nty, int nsy,
+                                                                      double *__restrict__ lt,
+                                                                      double *__restrict__ sst, Args a) {
     constexpr int NS = cascade_states(K);
+    __shared__ double zx[COL_WPB][2 * NS][64];
     const int lane = threadIdx.x & 63;
-    const int ty = blockIdx.y * COL_WPB + wave_id();
+    const int wv = wave_id();
+    const int sy = blockIdx.y;
+    const int ty = sy * COL_WPB + wv;
     const int s = blockIdx.z;
     const int col = blockIdx.x * 64 + lane;
-    if (ty >= nty) return;
     const int ccol = min(col, W - 1);
     const ScaleArgs &cf = a.s[s];
     const int y0 = ty * CT;
     static_assert(CT <= 64, "one row scale per lane");
-    const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
-    uint32_t xs[CT];
-#pragma unroll
-    for (int j = 0; j < CT; ++j) {
-        const int y = y0 + j;
-        const uint32_t v = m.raw(s, min(y, H - 1), ccol);
-        xs[j] = y < H ? v : 0u;  // zeros (in either format) after the last row
-    }                            // leave the backward zero state exact
+    auto tile_len = [&](int t) { return max(0, min(CT, H - t * CT)); };
     double zf[NS], zb[NS];
     set_zero(zf);
     set_zero(zb);
+    if (ty < nty) {   // tiles past the last row contribute zero states over zero rows
+        const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
+        uint32_t xs[CT];
 #pragma unroll
-    for (int j = 0; j < CT; ++j) cas_step<K>(cf, zf, m.cvt(xs[j], read_lane_d(lsc, j)));
+        for (int j = 0; j < CT; ++j) {
+            const int y = y0 + j;
+            const uint32_t v = m.raw(s, min(y, H - 1), ccol);
+            xs[j] = y < H ? v : 0u;  // zeros (in either format) after the last row
+        }                            // leave the backward zero state exact
 #pragma unroll
-    for (int j = CT - 1; j >= 0; --j) cas_step<K>(cf, zb, m.cvt(xs[j], read_lane_d(lsc, j)));
-    if (col < W) {
-        double *o = st + ((int64_t)(s * nty + ty) * 2 * NS) * W + col;
+        for (int j = 0; j < CT; ++j) cas_step<K>(cf, zf, m.cvt(xs[j], read_lane_d(lsc, j)));
+#pragma unroll
+        for (int j = CT - 1; j >= 0; --j) cas_step<K>(cf, zb, m.cvt(xs[j], read_lane_d(lsc, j)));
+    }
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        zx[wv][k][lane] = zf[k];
+        zx[wv][NS + k][lane] = zb[k];
+    }
+    __syncthreads();
+    if (col >= W) return;
+    auto zget = [&](int t, int k0, double (&z)[NS]) {
+#pragma unroll
+        for (int k = 0; k < NS; ++k) z[k] = zx[t][k0 + k][lane];
+    };
+    if (ty < nty) {
+        // forward: over the tiles above this one (all CT rows long); backward:
+        // over the tiles below it, from the super tile's bottom edge
+        double lf[NS], lb[NS], z[NS];
+        set_zero(lf);
+        set_zero(lb);
+        const Tr tfull = tr_n<K>(cf, CT);
+        for (int t = 0; t < wv; ++t) {
+            zget(t, 0, z);
+            cas_advance_add<K>(tfull, lf, z);
+        }
+        for (int t = COL_WPB - 1; t > wv; --t) {
+            zget(t, NS, z);
+            cas_advance_add<K>(tr_n<K>(cf, tile_len(sy * COL_WPB + t)), lb, z);
+        }
+        double *o = lt + ((int64_t)(s * nty + ty) * 2 * NS) * W + col;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            o[(int64_t)k * W] = zf[k];
-            o[(int64_t)(NS + k) * W] = zb[k];
+            o[(int64_t)k * W] = lf[k];
+            o[(int64_t)(NS + k) * W] = lb[k];
+        }
+    }
+    if (wv == 0) {
+        double sf[NS], sb[NS], z[NS];
+        set_zero(sf);
+        set_zero(sb);
+        for (int t = 0; t < COL_WPB; ++t) {
+            zget(t, 0, z);
+            cas_advance_add<K>(tr_n<K>(cf, tile_len(sy * COL_WPB + t)), sf, z);
+        }
+        for (int t = COL_WPB - 1; t >= 0; --t) {
+            zget(t, NS, z);
+            cas_advance_add<K>(tr_n<K>(cf, tile_len(sy * COL_WPB + t)), sb, z);
+        }
+        double *o = sst + ((int64_t)(s * nsy + sy) * 2 * NS) * W + col;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) {
+            o[(int64_t)k * W] = sf[k];
+            o[(int64_t)(NS + k) * W] = sb[k];
         }
     }
 }
 
-// (b) carries: in place, every tile's forward zero state becomes the forward
-// state entering the tile from above, every backward zero state the backward
-// state entering it from below.
-constexpr int SCAN_T = 64;  // threads (columns) per scan work-group
+// (b) carries: in place, every super tile's forward zero state becomes the
+// forward state entering it from above, every backward zero state the
+// backward state entering it from below.
+constexpr int SCAN_T = 64;        // threads (columns) per scan work-group
+constexpr int SCT = CT * COL_WPB;  // rows per super tile (transitions over up to 255 rows)
+static_assert(SCT < 256, "super-tile transitions from the eight binary powers");
 
 template <int K, bool FX>
 __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, int W, int nty,
                                                               double *__restrict__ st, Args a) {
+    // nty: super tiles of SCT rows
     constexpr int NS = cascade_states(K);
     constexpr int U = 8;  // tiles whose states are fetched together
     const int col = blockIdx.x * SCAN_T + threadIdx.x;
@@ -80,7 +144,7 @@ __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, 
     double c[NS];
 #pragma unroll
     for (int k = 0; k < NS; ++k) c[k] = rep ? xe * cf.ss[k] : 0.0;
-    const Tr tt = tr_n<K>(cf, CT);  // A^64
+    const Tr tt = tr_n<K>(cf, SCT);
     for (int i0 = 0; i0 < nty; i0 += U) {
         double z[U][NS];
 #pragma unroll
@@ -97,7 +161,7 @@ __global__ __launch_bounds__(SCAN_T) void iir_col_scan_kernel(Mid<FX> m, int H, 
             const int ty = dir == 0 ? i : nty - 1 - i;
 #pragma unroll
             for (int k = 0; k < NS; ++k) base[ty * tstride + (int64_t)k * W] = c[k];
-            const int len = min(CT, H - ty * CT);
+            const int len = min(SCT, H - ty * SCT);
             cas_advance_add<K>(len == CT ? tt : tr_n<K>(cf, len), c, z[u]);
         }
     }
@@ -154,7 +218,7 @@ constexpr int FIN_BLUR = 0, FIN_LAPLACIAN = 1, FIN_HESSIAN = 2;
 template <int K, int MODE, bool FX>
 __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
     Mid<FX> m, float *out, int64_t out_pitch, int64_t out_plane_stride, int H, int W, int nty, int ntx,
-    const double *__restrict__ st, Args a, HessArgs hz) {
+    const double *__restrict__ st, const double *__restrict__ sst, int nsy, Args a, HessArgs hz) {
     constexpr int NS = cascade_states(K);
     constexpr bool LAP = MODE != FIN_BLUR;   // second differences need the neighbour rows and columns
     constexpr int QT = 16;
@@ -187,12 +251,22 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
     const double lsc = m.row_scale(min(y0 + lane, H - 1));  // lane j: scale of row y0 + j
     double vf[NS], ub[NQ][NS];
     {
+        // the super tile's carries moved to this tile's edges (A^n over the
+        // zero-input rows between them), plus the tile's states within the
+        // super tile
+        const int sy = ty / COL_WPB;
+        const double *c = sst + ((int64_t)(s * nsy + sy) * 2 * NS) * W + ccol;
         const double *o = st + ((int64_t)(s * nty + ty) * 2 * NS) * W + ccol;
+        double lf[NS], lb[NS];
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            vf[k] = o[(int64_t)k * W];
-            ub[NQ - 1][k] = o[(int64_t)(NS + k) * W];
+            vf[k] = c[(int64_t)k * W];
+            ub[NQ - 1][k] = c[(int64_t)(NS + k) * W];
+            lf[k] = o[(int64_t)k * W];
+            lb[k] = o[(int64_t)(NS + k) * W];
         }
+        cas_advance_add<K>(tr_n<K>(cf, y0 - sy * SCT), vf, lf);
+        cas_advance_add<K>(tr_n<K>(cf, max(0, min(H, (sy + 1) * SCT) - y1)), ub[NQ - 1], lb);
     }
     double sc_above = 1.0, sc_below = 1.0;
     if constexpr (LAP && FX) {
@@ -331,19 +405,30 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
         body(std::false_type{});
 }
 
+// the tiles' states within their super tiles, then the super tiles' states
+int64_t tile_state_doubles(int64_t H, int64_t W, int nscales, int order) {
+    return (int64_t)nscales * ((H + CT - 1) / CT) * 2 * cascade_states(order) * W;
+}
+int64_t super_state_doubles(int64_t H, int64_t W, int nscales, int order) {
+    return (int64_t)nscales * ((H + SCT - 1) / SCT) * 2 * cascade_states(order) * W;
+}
+
 template <int K, bool FX>
 hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,
                           int mode, const HessArgs *hp, const IirParams &prm, double *st, hipStream_t stream) {
     Args a = make_args(prm, 1);
     const int nty = (int)((H + CT - 1) / CT);
+    const int nsy = (int)((H + SCT - 1) / SCT);
+    double *sst = st + tile_state_doubles(H, W, prm.nscales, K);
     const unsigned S = (unsigned)prm.nscales;
-    dim3 g1((unsigned)((W + 63) / 64), (unsigned)((nty + COL_WPB - 1) / COL_WPB), S);
+    dim3 g1((unsigned)((W + 63) / 64), (unsigned)nsy, S);
     hipLaunchKernelGGL((iir_col_states_kernel<K, FX>), g1, dim3(COL_WPB * 64), 0, stream, m, (int)H, (int)W, nty,
-                       st, a);
+                       nsy, st, sst, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     dim3 g2((unsigned)((W + SCAN_T - 1) / SCAN_T), S, 2);
-    hipLaunchKernelGGL((iir_col_scan_kernel<K, FX>), g2, dim3(SCAN_T), 0, stream, m, (int)H, (int)W, nty, st, a);
+    hipLaunchKernelGGL((iir_col_scan_kernel<K, FX>), g2, dim3(SCAN_T), 0, stream, m, (int)H, (int)W, nsy, sst,
+                       a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int ntyg = (nty + FIN_WPB - 1) / FIN_WPB;
@@ -353,15 +438,15 @@ hipError_t launch_cols_kx(Mid<FX> m, float *out, int64_t H, int64_t W, int64_t p
         const unsigned nb = (unsigned)ntx * (unsigned)ntyg * S;
         if (mode == FIN_HESSIAN)
             hipLaunchKernelGGL((iir_col_final_kernel<K, FIN_HESSIAN, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream,
-                               m, out, pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a, hz);
+                               m, out, pitch, plane_stride, (int)H, (int)W, nty, ntx, st, sst, nsy, a, hz);
         else
             hipLaunchKernelGGL((iir_col_final_kernel<K, FIN_LAPLACIAN, FX>), dim3(nb), dim3(FIN_WPB * 64), 0,
-                               stream, m, out, pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a, hz);
+                               stream, m, out, pitch, plane_stride, (int)H, (int)W, nty, ntx, st, sst, nsy, a, hz);
     } else {
         const int ntx = (int)((W + 63) / 64);
         const unsigned nb = (unsigned)ntx * (unsigned)ntyg * S;
         hipLaunchKernelGGL((iir_col_final_kernel<K, FIN_BLUR, FX>), dim3(nb), dim3(FIN_WPB * 64), 0, stream, m, out,
-                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, a, hz);
+                           pitch, plane_stride, (int)H, (int)W, nty, ntx, st, sst, nsy, a, hz);
     }
     return hipGetLastError();
 }
@@ -380,8 +465,8 @@ hipError_t launch_cols_k(const void *in, int64_t in_pitch, int64_t in_plane_stri
 }  // namespace
 
 size_t iir_cols_workspace_bytes(int64_t H, int64_t W, int nscales, int order) {
-    const int64_t nty = (H + CT - 1) / CT;
-    return ((size_t)nscales * nty * 2 * cascade_states(order) * W * sizeof(double) + 255) & ~(size_t)255;
+    const int64_t n = tile_state_doubles(H, W, nscales, order) + super_state_doubles(H, W, nscales, order);
+    return ((size_t)n * sizeof(double) + 255) & ~(size_t)255;
 }
 
 hipError_t launch_iir_cols(const void *in, int64_t in_pitch, int64_t in_plane_stride, const int *rexp, float *out,

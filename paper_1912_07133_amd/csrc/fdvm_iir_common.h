@@ -48,7 +48,7 @@ struct ScaleArgs {
     double pim, inv_pim;         // complex pair: imaginary parts of p and 1/p
     double w[MAX_SECTIONS];
     double ss[MAX_SECTIONS];
-    double pbit[7];    // real pole: p^(2^k), k = 0..6
+    double pbit[8];    // real pole: p^(2^k), k = 0..7
     double pchunk[7];  // real pole, row pass: p^(C 2^k), k = 0..6
 };
 
@@ -179,11 +179,11 @@ __device__ __forceinline__ void set_zero(double (&v)[N]) {
     for (int k = 0; k < N; ++k) v[k] = 0.0;
 }
 
-// p^n for 0 <= n < 128 from the binary powers
+// p^n for 0 <= n < 256 from the binary powers
 __device__ __forceinline__ double pow_bits(const ScaleArgs &c, int n) {
     double r = 1.0;
 #pragma unroll
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 8; ++k)
         if ((n >> k) & 1) r *= c.pbit[k];
     return r;
 }
@@ -213,7 +213,7 @@ __device__ __forceinline__ Tr cpow(const ScaleArgs &c, int n) {
     return {rr, ri};
 }
 
-// transitions over n < 128 samples, C m samples (m < 128), C 2^l samples
+// transitions over n < 256 samples, C m samples (m < 128), C 2^l samples
 template <int K>
 __device__ __forceinline__ Tr tr_n(const ScaleArgs &c, int n) {
     if constexpr (K == CPAIR)
@@ -300,10 +300,10 @@ Args make_args(const IirParams &prm, int C) {
             d.w[k] = q.w[k];
             d.ss[k] = q.ss[k];
         }
-        for (int k = 0; k < 7 && prm.order != CPAIR; ++k) {   // complex powers are formed in the kernels
+        for (int k = 0; k < 8 && prm.order != CPAIR; ++k)   // complex powers are formed in the kernels
             d.pbit[k] = std::exp((double)(1 << k) * q.lnp);
+        for (int k = 0; k < 7 && prm.order != CPAIR; ++k)
             d.pchunk[k] = std::exp((double)C * (double)(1 << k) * q.lnp);
-        }
     }
     return a;
 }
