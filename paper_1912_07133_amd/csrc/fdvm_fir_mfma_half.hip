@@ -116,6 +116,17 @@ __device__ __forceinline__ void split(float v, uint16_t &hi, uint16_t &lo) {
     lo = Op<H>::bits((v - Op<H>::value(hi)) * Op<H>::lo_scale);
 }
 
+// wait until at most N vector-memory operations of this wavefront are in
+// flight (s_waitcnt with the expcnt and lgkmcnt fields at their no-wait
+// maxima; vmcnt split over bits 3:0 and 15:14).  The builtin, unlike an asm
+// block, is seen by the compiler's own wait tracking, which then knows that
+// the copies issued before those N operations have landed in LDS.
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 0xf) | (0x7 << 4) | (0xf << 8) | ((N >> 4) << 14));
+}
+
 __device__ __forceinline__ int xcd_logical(int hw, int n) {
     constexpr int NX = 8;
     const int xcd = hw % NX, slot = hw / NX;
@@ -192,16 +203,67 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     const int NE = table_entries(KP);
     const int NG = KP / 8 + 4;   // groups: 2 K'/16 + 4
     const int C0 = KP + 56;
-    {
-        const u32x4 *tg = tables + hs.tab[s];
-        for (int e = threadIdx.x; e < 2 * NE; e += blockDim.x) lds[e] = tg[e];
-    }
-    __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int p0 = (pg * HT_WPOS + wv % HT_WPOS) * HT_POS;
     const int y0 = (rt * HT_WROW + wv / HT_WPOS) * HT_ROWS;
-    if (p0 >= n || y0 >= R_out) return;   // no barrier follows
+    const bool live = p0 < n && y0 < R_out;   // wave-uniform
+    // FAST: chunks of four groups (64 samples of the wavefront's 32 rows) are
+    // fetched with whole-line loads (lane l: row 8 j + l / 8, 16-byte segment
+    // l % 8; every instruction reads 8 full 128-byte lines), AHEAD chunks in
+    // flight, chunk c in slot c % AHEAD.  Two for pair sources; one for the
+    // first pass, whose register budget would otherwise cost a wavefront per
+    // SIMD.
+    constexpr int AHEAD = PAIR ? 2 : 1;
+    const int lr = lane >> 3, lq = lane & 7;
+    int64_t roffs[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        roffs[j] = (int64_t)s * src_plane + (int64_t)min(y0 + 8 * j + lr, R - 1) * src_pitch;
+    u32x4 fa[4], fla[4], fb[4], flb[4];
+    auto gload = [&](int c, u32x4(&fh)[4], u32x4(&fl)[4]) {
+        const int c0 = p0 - KP + 64 * c + 8 * lq;
+        const int cl = min(max(c0, 0), n_in - 8);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            fh[j] = *reinterpret_cast<const u32x4 *>(src + roffs[j] + cl);
+            if constexpr (PAIR) fl[j] = *reinterpret_cast<const u32x4 *>(src_lo + roffs[j] + cl);
+        }
+    };
+    {
+        const u32x4 *tg = tables + hs.tab[s];
+        if constexpr (FAST) {
+            // the table straight into LDS, 16 bytes per lane (the last round's
+            // spare lanes land in the padding before the staging buffers),
+            // then the first chunks: only the table is waited for before the
+            // barrier, so their latency overlaps the copy
+            for (int e0 = 0; e0 < 2 * NE; e0 += HT_WPB * 64)
+                __builtin_amdgcn_global_load_lds((const void *)(tg + min(e0 + (int)threadIdx.x, 2 * NE - 1)),
+                                                 (__attribute__((address_space(3))) void *)(lds + e0 + wv * 64),
+                                                 16, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+            if (live) {
+                gload(0, fa, fla);
+                if constexpr (AHEAD == 2) gload(1, fb, flb);
+                __builtin_amdgcn_sched_barrier(0);
+                wait_vm<(PAIR ? 8 : 4) * AHEAD>();
+            } else {
+                wait_vm<0>();
+            }
+        } else {
+            for (int e = threadIdx.x; e < 2 * NE; e += blockDim.x) lds[e] = tg[e];
+        }
+    }
+    if constexpr (FAST) {
+        // every wavefront has waited for its own copies of the table; a plain
+        // barrier (no fence) lets the first chunks stay in flight across it
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_barrier();
+        asm volatile("" ::: "memory");
+    } else {
+        __syncthreads();
+    }
+    if (!live) return;   // no barrier follows
     const int i = lane & 31;   // A: row y0 + i; B and D: output p0 + 32 t + i
     const int g8 = lane >> 5;  // which eight of the group's sixteen samples
     const int row = min(y0 + i, R - 1);
@@ -252,9 +314,9 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
         l0[e] = 0.0f;
         l1[e] = 0.0f;
     }
-    // block 0's tap fragment of group g in slot g % 4 (block 1 uses it two
-    // groups later)
-    u32x4 bh[4], bl[4];
+    // block 0's tap fragment of group g is entry ebase - 16 g; block 1's is
+    // block 0's of group g - 2, read again rather than kept (a register ring
+    // of fragments would cost the kernel a wavefront per SIMD)
     const int ebase = C0 + KP + i - 8 * g8;   // block 0's entry at group 0
     // the products of group g from its raw samples vh (and vl)
     auto mma = [&](int g, u32x4 vh, u32x4 vl, auto slot_c, auto blocks_c) {
@@ -270,17 +332,18 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
             if constexpr (PAIR) al = vl;
         }
         if constexpr (BL & 1) {
-            bh[k] = lds[ebase - HT_G * g];
-            bl[k] = lds[NE + ebase - HT_G * g];
-            m0 = Op<H>::mfma(ah, bh[k], m0);
-            l0 = Op<H>::mfma(ah, bl[k], l0);
-            if constexpr (SPLIT) l0 = Op<H>::mfma(al, bh[k], l0);
+            const u32x4 bh = lds[ebase - HT_G * g];
+            const u32x4 bl = lds[NE + ebase - HT_G * g];
+            m0 = Op<H>::mfma(ah, bh, m0);
+            l0 = Op<H>::mfma(ah, bl, l0);
+            if constexpr (SPLIT) l0 = Op<H>::mfma(al, bh, l0);
         }
         if constexpr (BL & 2) {
-            constexpr int q = (k + 2) % 4;
-            m1 = Op<H>::mfma(ah, bh[q], m1);
-            l1 = Op<H>::mfma(ah, bl[q], l1);
-            if constexpr (SPLIT) l1 = Op<H>::mfma(al, bh[q], l1);
+            const u32x4 bh = lds[ebase - HT_G * (g - 2)];
+            const u32x4 bl = lds[NE + ebase - HT_G * (g - 2)];
+            m1 = Op<H>::mfma(ah, bh, m1);
+            l1 = Op<H>::mfma(ah, bl, l1);
+            if constexpr (SPLIT) l1 = Op<H>::mfma(al, bh, l1);
         }
     };
     using I = std::integral_constant<int, 0>;
@@ -290,38 +353,17 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     // block 0 alone for groups 0, 1; both for 2 .. NG - 3 (K'/8 groups, a
     // multiple of 4); block 1 alone for NG - 2, NG - 1
     if constexpr (FAST) {
-        // Chunks of four groups (64 samples of the wavefront's 32 rows, 4 KB
-        // per plane) are fetched one chunk ahead into registers with whole-
-        // line loads (lane l: row 8 j + l / 8, 16-byte segment l % 8; every
-        // instruction reads 8 full 128-byte lines), then written to this
-        // wavefront's LDS buffer with the segment of row r at slot
-        // segment ^ (r % 8), so that the A fragments (lane i + 32 g: row i,
-        // segment 2 (g % 4) + g) come back conflict-free.  The buffer is the
-        // wavefront's own and LDS operations of a wavefront complete in order,
-        // so no barrier is needed between a chunk's reads and the next write.
+        // Each chunk (fetched before the barrier for the first AHEAD) is
+        // written to this wavefront's LDS buffer with the segment of row r at
+        // slot segment ^ (r % 8), so that the A fragments (lane i + 32 g: row
+        // i, segment 2 (g % 4) + g) come back conflict-free, and its slot is
+        // refilled with chunk c + AHEAD (the last chunk again at the end: an
+        // L1 hit).  The buffer is the wavefront's own and LDS operations of a
+        // wavefront complete in order, so no barrier is needed between a
+        // chunk's reads and the next write.
         u32x4 *sh = lds + stage_off + wv * (PAIR ? 512 : 256);
         u32x4 *sl = sh + 256;
         const int NC = NG / 4;   // >= 2 (K' >= 32)
-        const int lr = lane >> 3, lq = lane & 7;
-        int64_t roffs[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-            roffs[j] = (int64_t)s * src_plane + (int64_t)min(y0 + 8 * j + lr, R - 1) * src_pitch;
-        // AHEAD chunks in flight: chunk c in slot c % AHEAD, refilled with
-        // chunk c + AHEAD once written to LDS (the last chunk again at the
-        // end: an L1 hit).  Two for pair sources; one for the first pass,
-        // whose register budget would otherwise cost a wavefront per SIMD
-        constexpr int AHEAD = PAIR ? 2 : 1;
-        u32x4 fa[4], fla[4], fb[4], flb[4];
-        auto gload = [&](int c, u32x4(&fh)[4], u32x4(&fl)[4]) {
-            const int c0 = p0 - KP + 64 * c + 8 * lq;
-            const int cl = min(max(c0, 0), n_in - 8);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                fh[j] = *reinterpret_cast<const u32x4 *>(src + roffs[j] + cl);
-                if constexpr (PAIR) fl[j] = *reinterpret_cast<const u32x4 *>(src_lo + roffs[j] + cl);
-            }
-        };
         const int rsw = i & 7;
         auto chunk = [&](int c, auto kind_c, u32x4(&fh)[4], u32x4(&fl)[4]) {
             constexpr int KIND = decltype(kind_c)::value;   // 0 first, 1 middle, 2 last
@@ -330,6 +372,9 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
                 sh[(8 * j + lr) * 8 + (lq ^ lr)] = fh[j];
                 if constexpr (PAIR) sl[(8 * j + lr) * 8 + (lq ^ lr)] = fl[j];
             }
+            // the refill after the writes: hoisted above them, it would be
+            // waited for with them
+            __builtin_amdgcn_sched_barrier(0);
             gload(min(c + AHEAD, NC - 1), fh, fl);
             // keep the refill here: the scheduler would otherwise sink it
             __builtin_amdgcn_sched_barrier(0);
@@ -351,9 +396,7 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
         using FIRST = std::integral_constant<int, 0>;
         using MID = std::integral_constant<int, 1>;
         using LAST = std::integral_constant<int, 2>;
-        gload(0, fa, fla);
         if constexpr (AHEAD == 2) {
-            gload(1, fb, flb);
             chunk(0, FIRST{}, fa, fla);
             int c = 1;
             for (; c + 2 < NC; c += 2) {
@@ -542,7 +585,8 @@ hipError_t rows_pass(const void *src, const void *src_lo, int64_t src_pitch, int
                      hipStream_t st) {
     const unsigned nrt = (unsigned)((R_out + HT_ROWS * HT_WROW - 1) / (HT_ROWS * HT_WROW));
     const unsigned npg = (unsigned)((n + HT_POS * HT_WPOS - 1) / (HT_POS * HT_WPOS));
-    const int stage_off = 2 * table_entries(kp_max);
+    // the table's direct copies write whole rounds of HT_WPB * 64 entries
+    const int stage_off = ((2 * table_entries(kp_max) + HT_WPB * 64 - 1) / (HT_WPB * 64)) * (HT_WPB * 64);
     const int stage = FAST ? HT_WPB * (SRC == SRC_PAIR ? 512 : 256) : 0;   // 16-byte entries
     const size_t lds = sizeof(u32x4) * (size_t)(stage_off + stage);
     hipLaunchKernelGGL((fir_half_rows_kernel<H, SRC, OUT_F32, FAST>), dim3(nrt * npg * (unsigned)hs.nscales),
