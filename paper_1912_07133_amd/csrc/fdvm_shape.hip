@@ -148,6 +148,11 @@ __device__ __forceinline__ int key_right(int k) { return __builtin_amdgcn_mov_dp
 // magnitude higher); for c > 0, c > n exactly when bits(c) > bits(n) as signed
 // integers.  The statistics are then the unsigned and the signed maximum of
 // the raw bits (sentinels 0 and INT32_MIN), and no key transform is needed.
+// The thresholds join them the same way: c <= -tau exactly when bits(c) >
+// bits(-tau) - 1 unsigned, c >= tau exactly when bits(c) > bits(tau) - 1
+// signed; taken into every row's left/right maximum, they reach each
+// decision through the centre plane's 8-neighbour statistic, and a candidate
+// is one unsigned and one signed comparison.
 // Otherwise (tau = 0, where a zero centre may be an extremum) they are the
 // minimum and maximum of order-preserving keys (fkey; sentinels INT32_MAX and
 // INT32_MIN).
@@ -207,6 +212,10 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     };
     auto hi2 = [](int a, int b) { return max(a, b); };
     auto hi3 = [](int a, int b, int c) { return max(max(a, b), c); };
+    // RAW: the thresholds as raw-bit floors of the two statistics (below);
+    // otherwise the statistics' sentinels, which change nothing
+    const int tlo = RAW ? (int)(__float_as_uint(-tau) - 1u) : LO_NONE;
+    const int thi = RAW ? __float_as_int(tau) - 1 : HI_NONE;
     // statistics of plane s (its copies must have landed).  EDGE: the band
     // touches the image border (some rows or lanes outside get sentinels);
     // otherwise every staged sample is inside and no test is needed.
@@ -222,16 +231,16 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
                 const int y = y0 - 1 + r;
                 const bool yin = y >= 0 && y < H;   // wave-uniform
                 const int klo = xin ? k : LO_NONE, khi = xin ? k : HI_NONE;
-                const int l = lo2(key_left(klo), key_right(klo));
-                const int h = hi2(key_left(khi), key_right(khi));
+                const int l = lo3(key_left(klo), key_right(klo), tlo);
+                const int h = hi3(key_left(khi), key_right(khi), thi);
                 llo[r] = yin ? l : LO_NONE;
                 lhi[r] = yin ? h : HI_NONE;
                 rlo[r] = yin ? lo2(l, klo) : LO_NONE;
                 rhi[r] = yin ? hi2(h, khi) : HI_NONE;
             } else {
                 const int kl = key_left(k), kr = key_right(k);
-                llo[r] = lo2(kl, kr);
-                lhi[r] = hi2(kl, kr);
+                llo[r] = lo3(kl, kr, tlo);
+                lhi[r] = hi3(kl, kr, thi);
                 rlo[r] = lo3(kl, kr, k);
                 rhi[r] = hi3(kl, kr, k);
             }
@@ -256,6 +265,10 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     const bool xout = lane >= 1 && lane <= 62 && x < W && x >= border && x < W - border;
     unsigned long long *wd = words[wv];
     // decisions at plane s from its neighbours in scale
+    // the decided columns as a lane mask; ballots are taken of single
+    // comparisons and combined on the scalar unit (a ballot of a combined
+    // condition is rebuilt through a vector register)
+    const unsigned long long xmask = __builtin_amdgcn_ballot_w64(xout);
     auto decide = [&](int s, const Plane &pv, const Plane &pc, const Plane &pn) {
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -263,18 +276,16 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
             const int lo = lo3(pc.lo8[r], pv.lo9[r], pn.lo9[r]);
             const int hi = hi3(pc.hi8[r], pv.hi9[r], pn.hi9[r]);
             const int k = pc.c[r];
-            const bool inside = xout && y < H && y >= border && y < H - border;
+            const bool yin = y < H && y >= border && y < H - border;   // wave-uniform
             // no neighbour at all (1 x 1 x 1 stack) compares as "strict" too
-            bool bright, dark;
-            if constexpr (RAW) {
-                const float v = __int_as_float(k);
-                bright = inside && v <= -tau && (unsigned)k > (unsigned)lo;
-                dark = inside && v >= tau && k > hi;
+            unsigned long long hit;
+            if constexpr (RAW) {   // the thresholds are inside lo and hi
+                hit = __builtin_amdgcn_ballot_w64((unsigned)k > (unsigned)lo) | __builtin_amdgcn_ballot_w64(k > hi);
             } else {
-                bright = inside && k <= kneg && k < lo;
-                dark = inside && k >= kpos && k > hi;
+                hit = (__builtin_amdgcn_ballot_w64(k <= kneg) & __builtin_amdgcn_ballot_w64(k < lo)) |
+                      (__builtin_amdgcn_ballot_w64(k >= kpos) & __builtin_amdgcn_ballot_w64(k > hi));
             }
-            const unsigned long long bits = __ballot(bright || dark) >> 1;  // lanes 1..62 -> bits 0..61
+            const unsigned long long bits = yin ? (hit & xmask) >> 1 : 0ull;   // lanes 1..62 -> bits 0..61
             if (lane == 0) wd[s * RB + r] = bits;
         }
     };
@@ -286,15 +297,25 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         wait_vm<AHEAD>();   // plane 0
         stats(0, P0, edge_tag);
         // step at plane s: plane s + 1 is needed now; plane s's slot is free
-        // (its statistics are in registers)
+        // (its statistics are in registers).  After the last plane the centre
+        // plane's own 8-neighbour statistics stand in for the missing 3 x 3
+        // ones (the maximum of a value with itself changes nothing), so no
+        // sentinel plane is formed inside the loop.
         auto step = [&](int s, Plane &pv, Plane &pc, Plane &pn) {
             request(s + DT_NPL);
             wait_vm<AHEAD>();
-            if (s + 1 < S)
+            if (s + 1 < S) {
                 stats(s + 1, pn, edge_tag);
-            else
-                absent(pn);
-            decide(s, pv, pc, pn);
+                decide(s, pv, pc, pn);
+            } else {
+                Plane own;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    own.lo9[r] = pc.lo8[r];
+                    own.hi9[r] = pc.hi8[r];
+                }
+                decide(s, pv, pc, own);
+            }
         };
         for (int s = 0; s < S; s += 3) {
             step(s, P2, P0, P1);
