@@ -91,11 +91,13 @@ __global__ __launch_bounds__(COL_WPB * 64) void iir_col_states_kernel(Mid<FX> m,
             zget(t, NS, z);
             cas_advance_add<K>(tr_n<K>(cf, tile_len(sy * COL_WPB + t)), lb, z);
         }
+        // the first tile's forward state and the last tile's backward state
+        // are zero by definition: not stored (nor read by the final pass)
         double *o = lt + ((int64_t)(s * nty + ty) * 2 * NS) * W + col;
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
-            o[(int64_t)k * W] = lf[k];
-            o[(int64_t)(NS + k) * W] = lb[k];
+            if (wv > 0) o[(int64_t)k * W] = lf[k];
+            if (wv < COL_WPB - 1) o[(int64_t)(NS + k) * W] = lb[k];
         }
     }
     if (wv == 0) {
@@ -254,16 +256,24 @@ __global__ __launch_bounds__(FIN_WPB * 64) void iir_col_final_kernel(
         // the super tile's carries moved to this tile's edges (A^n over the
         // zero-input rows between them), plus the tile's states within the
         // super tile
-        const int sy = ty / COL_WPB;
+        const int sy = ty / COL_WPB, w = ty % COL_WPB;   // wave-uniform
         const double *c = sst + ((int64_t)(s * nsy + sy) * 2 * NS) * W + ccol;
         const double *o = st + ((int64_t)(s * nty + ty) * 2 * NS) * W + ccol;
         double lf[NS], lb[NS];
+        set_zero(lf);   // the first tile's forward and the last tile's backward
+        set_zero(lb);   // states are zero (not stored)
 #pragma unroll
         for (int k = 0; k < NS; ++k) {
             vf[k] = c[(int64_t)k * W];
             ub[NQ - 1][k] = c[(int64_t)(NS + k) * W];
-            lf[k] = o[(int64_t)k * W];
-            lb[k] = o[(int64_t)(NS + k) * W];
+        }
+        if (w > 0) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) lf[k] = o[(int64_t)k * W];
+        }
+        if (w < COL_WPB - 1) {
+#pragma unroll
+            for (int k = 0; k < NS; ++k) lb[k] = o[(int64_t)(NS + k) * W];
         }
         cas_advance_add<K>(tr_n<K>(cf, y0 - sy * SCT), vf, lf);
         cas_advance_add<K>(tr_n<K>(cf, max(0, min(H, (sy + 1) * SCT) - y1)), ub[NQ - 1], lb);
