@@ -504,7 +504,7 @@ def main() -> int:
     # oracle in the CPU-baseline leg.  The float32 blur alone, direct and on
     # the matrix cores, is timed beside it.
     fir = None
-    V_fir = det_fir = None
+    V_fir = det_fir = V_firm = det_firm = None
     if not args.no_fir:
         taps_d, half, off = P.fir_taps_device("sg", sig, None, dev)
         taps, _, _ = P.fir_taps("sg", sig)
@@ -512,6 +512,8 @@ def main() -> int:
         ws_fir = torch.empty(P.workspace_bytes(P.OP_BLUR_FIR, H, W, S, int(half.max())), dtype=torch.uint8,
                              device=dev)
         ws_firlap = torch.empty(P.workspace_bytes(P.OP_FIR_LAPLACIAN, H, W, S), dtype=torch.uint8, device=dev)
+        ws_firlapm = torch.empty(P.workspace_bytes(P.OP_FIR_LAPLACIAN_MFMA, H, W, S), dtype=torch.uint8,
+                                 device=dev)
         dp, ip = ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)
 
         sig_from = [(ctypes.c_double * (S - s0))(*sig[s0:]) for s0 in range(S)]
@@ -526,6 +528,17 @@ def main() -> int:
 
         def fir_step(ev):
             fir_fused(ev)
+            detect_into(ev[2])
+
+        sig_all = (ctypes.c_double * S)(*sig)
+
+        def fir_step_mfma(ev):
+            ev[0].record(stream)
+            check(L.fdvm_fir_laplacian_mfma(x.data_ptr(), P.U16, H, W, W, V.data_ptr(), W, H * W,
+                                            taps.ctypes.data_as(dp), half.ctypes.data_as(ip),
+                                            off.ctypes.data_as(ip), sig_all, S, P.BC_REPLICATE,
+                                            ws_firlapm.data_ptr(), ws_firlapm.numel(), sp), "fir_laplacian_mfma")
+            ev[1].record(stream)
             detect_into(ev[2])
 
         def fir_blur_for(algo):
@@ -553,6 +566,19 @@ def main() -> int:
                         "detections": n_fir, "step": "fdvm_fir_laplacian (float64 FIR passes) + detection"}
         log(f"FIR fused: {fms:.4f} ms/step, {fir['fused']['value']:.0f} Mpx*scales/s "
             f"(fir_laplacian {fper[0]:.3f} ms), detections {n_fir}")
+        # the same detection response on the matrix cores (two-stage band-pass)
+        mtot, _, mper = timed(fir_step_mfma, 3, fsteps, max(1, args.warmup // 5))
+        mms = mtot / fsteps
+        n_firm = int(count.item())
+        V_firm = V.cpu().numpy()
+        det_firm = blobs[: min(n_firm, cap) * P.BLOB_BYTES].cpu().numpy().view(P.BLOB_DTYPE).copy()
+        fir["fused_mfma"] = {"value": round(mpx / (mms / 1e3), 1), "ms_per_step": round(mms, 4),
+                             "fir_laplacian_ms": round(mper[0], 4), "detect_ms": round(mper[1], 4),
+                             "detections": n_firm,
+                             "step": "fdvm_fir_laplacian_mfma (matrix cores, float16 operand pairs, the two-stage "
+                                     "band-pass h(y) d(x) + d(y) h(x), d = h * [1, -2, 1]) + detection"}
+        log(f"FIR fused (matrix cores): {mms:.4f} ms/step, {fir['fused_mfma']['value']:.0f} Mpx*scales/s "
+            f"(fir_laplacian_mfma {mper[0]:.3f} ms), detections {n_firm}")
         fir["blur_only"] = {}
         arith = {"direct": "float32", "mfma": "float32 operands and accumulation",
                  "mfma_half": "float16 operand pairs (exact split of the uint16 samples), float32 accumulation"}
@@ -699,6 +725,27 @@ def main() -> int:
                                    "sample": "the same frame and scales through the FIR oracle (coloured SG, "
                                              "matrix form of the separable sum), one scale per worker process"}
             log(f"FIR parity {fir['parity']}")
+            if V_firm is not None:
+                # a-priori bound of the matrix-core route: sigma^2 (sum |h|) (sum |d|) max |x|
+                # (12 2^-22 + (4 n + 2) 2^-24) plus the float32 rounding of V
+                xmax = float(frame.max())
+                vbm = []
+                for s, sg in enumerate(sig):
+                    h_s = np.asarray(taps[off[s]: off[s] + 2 * half[s] + 1], np.float64)
+                    hpad = np.concatenate([[0.0, 0.0], h_s, [0.0, 0.0]])
+                    d_s = hpad[:-2] - 2 * hpad[1:-1] + hpad[2:]
+                    n_s = 2 * int(half[s]) + 3
+                    vbm.append(sg * sg * float(np.sum(np.abs(h_s))) * float(np.sum(np.abs(d_s))) * xmax *
+                               (12 * 2.0 ** -22 + (4 * n_s + 2) * 2.0 ** -24) +
+                               2.0 ** -23 * float(np.max(np.abs(Vf[s]))))
+                vratio_m = max(float(np.max(np.abs(V_firm[s] - Vf[s]))) / vbm[s] for s in range(S))
+                nfrag_m, mism_m = compare_detections(det_firm, det_ref_f, Vf, V_firm, tau, border, v_bound=vbm)
+                fir["parity_mfma"] = {"err_over_bound": round(vratio_m, 4), "detections": int(len(det_firm)),
+                                      "oracle_detections": int(len(det_ref_f)), "fragile_excluded": nfrag_m,
+                                      "mismatches": len(mism_m),
+                                      "ok": bool(vratio_m <= 1.0 and not mism_m and
+                                                 nfrag_m <= 0.001 * V_firm.size)}
+                log(f"FIR matrix-core parity {fir['parity_mfma']}")
             del Bf, Vf
         if precision is not None:
             precision_errors(precision, syn, torch, np, log)

@@ -426,11 +426,49 @@ fdvm_status fdvm_fir_laplacian_backward(const void *x, fdvm_dtype dt, int64_t H,
 /* workspace sizes */
 enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_IIR_LAPLACIAN = 3,
        FDVM_OP_BLUR_IIR_ADJOINT = 4, FDVM_OP_PLANE_DOTS = 5, FDVM_OP_IIR_HESSIAN = 6,
-       FDVM_OP_FIR_LAPLACIAN = 7, FDVM_OP_IIR_LAPLACIAN_BACKWARD = 8, FDVM_OP_FIR_LAPLACIAN_BACKWARD = 9 };
+       FDVM_OP_FIR_LAPLACIAN = 7, FDVM_OP_IIR_LAPLACIAN_BACKWARD = 8, FDVM_OP_FIR_LAPLACIAN_BACKWARD = 9,
+       FDVM_OP_FIR_LAPLACIAN_MFMA = 10 };
 
 /* Bytes of device workspace `op` needs for an H x W frame with nscales
  * scales and maximum FIR half-length max_half_len (0 if unused). */
 size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len);
+
+/* Largest FIR half-length of fdvm_fir_laplacian_mfma: both tap sets of a
+ * scale (K + 2 coefficients each) must fit one launch's argument table. */
+#define FDVM_MAX_FIR_LAP_MFMA_HALF 438
+
+/*
+ * fdvm_fir_laplacian_mfma -- the FIR detection response of
+ *   fdvm_fir_laplacian (the same V_s = sigma_s^2 (D20 + D02) B_s, Section 5
+ *   and Table I on the blur of Eq A5) on the matrix cores with
+ *   half-precision operands, as the two-stage band-pass of Section 5:
+ *   with d_s = h_s * [1, -2, 1], V_s = sigma_s^2 (h_s(y) d_s(x) x +
+ *   d_s(y) h_s(x) x), the x pass forming both row filters and the y pass
+ *   both column filters (FDVM_FIR_TOEPLITZ_MFMA_HALF's operand pairs and
+ *   float32 accumulation); no blur plane is formed or rounded.  The
+ *   first and last rows and columns, where the differences of
+ *   fdvm_fir_laplacian take the replicate extension of B_s and these
+ *   filters the extension of the frame, are corrected in float64.
+ *   Error against the float64 response: at most sigma_s^2 (sum |h_s|)
+ *   (sum |d_s|) max |x| (12 2^-2p + (4 n + 2) 2^-24), p = 11 (float16 operands:
+ *   F16 and U16 frames) or 8 (BF16), n = 2 K_s + 3 accumulated terms per pass
+ *   (split taps and samples, the stored split intermediate, float32 sums and
+ *   the float32 partial response between the two y filters).
+ *   in, dt   F16, BF16 or U16 (F32 is rejected with FDVM_EINVAL, as for
+ *            FDVM_FIR_TOEPLITZ_MFMA_HALF); image arguments and out as
+ *            fdvm_iir_laplacian.
+ *   taps, half_len, tap_offset  HOST, as fdvm_blur_fir (symmetric taps);
+ *            K_s in [1, FDVM_MAX_FIR_LAP_MFMA_HALF].
+ *   sigmas   host float64[nscales], > 0.
+ *   ws, ws_bytes device workspace of at least
+ *            fdvm_workspace_bytes(FDVM_OP_FIR_LAPLACIAN_MFMA, H, W, nscales, 0).
+ * Returns FDVM_EINVAL / FDVM_ERANGE / FDVM_ENOMEM / FDVM_EUNSUPPORTED (no
+ * matrix cores) / FDVM_EDEVICE.
+ */
+fdvm_status fdvm_fir_laplacian_mfma(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                                    float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                                    const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                                    int nscales, fdvm_boundary bc, void *ws, size_t ws_bytes, void *stream);
 
 /*
  * fdvm_highpass -- Table I interpolating differences of blur planes with

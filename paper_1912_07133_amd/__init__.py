@@ -35,7 +35,8 @@ U16, F32, F16, BF16 = 0, 1, 2, 3
 FIR_DIRECT, FIR_TOEPLITZ_MFMA, FIR_TOEPLITZ_MFMA_HALF = 0, 1, 2
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
 (OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN,
- OP_FIR_LAPLACIAN, OP_IIR_LAPLACIAN_BACKWARD, OP_FIR_LAPLACIAN_BACKWARD) = range(10)
+ OP_FIR_LAPLACIAN, OP_IIR_LAPLACIAN_BACKWARD, OP_FIR_LAPLACIAN_BACKWARD, OP_FIR_LAPLACIAN_MFMA) = range(11)
+MAX_FIR_LAP_MFMA_HALF = 438
 GRAD_X, GRAD_SIGMA = 1, 2
 MAX_SCALES = 16
 MAX_FIR_HALF = 512
@@ -118,6 +119,10 @@ def lib() -> ctypes.CDLL:
         L.fdvm_fir_laplacian.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, vp, ctypes.POINTER(i32),
                                          ctypes.POINTER(i32), ctypes.POINTER(dbl), ctypes.c_int, ctypes.c_int, vp,
                                          ctypes.c_size_t, vp]
+        L.fdvm_fir_laplacian_mfma.restype = ctypes.c_int
+        L.fdvm_fir_laplacian_mfma.argtypes = [vp, ctypes.c_int, i64, i64, i64, vp, i64, i64, ctypes.POINTER(dbl),
+                                              ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(dbl),
+                                              ctypes.c_int, ctypes.c_int, vp, ctypes.c_size_t, vp]
         L.fdvm_highpass.restype = ctypes.c_int
         L.fdvm_highpass.argtypes = [vp, i64, i64, i64, i64, ctypes.c_int, ctypes.POINTER(dbl),
                                     ctypes.c_uint, ctypes.c_int, vp, i64, vp]
@@ -390,19 +395,36 @@ _DEVICE_TAPS: dict = {}
 
 
 def fir_laplacian(x, sigmas: Sequence[float], kind: str = "sg", half_lens: Sequence[int] | None = None,
-                  boundary: str = "replicate", out=None, workspace=None):
-    """FIR blur + normalised Laplacian in one call (fdvm_fir_laplacian):
-    [H, W] -> float32 V [S, H, W]."""
+                  boundary: str = "replicate", out=None, workspace=None, algo: int = FIR_DIRECT, taps=None):
+    """FIR blur + normalised Laplacian in one call: [H, W] -> float32 V [S, H, W].
+    algo FIR_DIRECT: fdvm_fir_laplacian (float64 passes); FIR_TOEPLITZ_MFMA_HALF:
+    fdvm_fir_laplacian_mfma (matrix cores, half-precision operand pairs; float16,
+    bfloat16 or uint16 frames), `taps` optionally a precomputed fir_taps triple."""
     torch = _torch()
     x = _frame(x)
     H, W = x.shape
     S = len(sigmas)
-    taps, half, off = fir_taps_device(kind, sigmas, half_lens, x.device)
     if out is None:
         out = torch.empty((S, H, W), dtype=torch.float32, device=x.device)
-    ws = _workspace(OP_FIR_LAPLACIAN, H, W, S, x.device, workspace)
-    ip = ctypes.POINTER(ctypes.c_int32)
     sig = (ctypes.c_double * S)(*[float(s) for s in sigmas])
+    ip = ctypes.POINTER(ctypes.c_int32)
+    if algo == FIR_TOEPLITZ_MFMA_HALF:
+        t, half, off = taps if taps is not None else fir_taps(kind, sigmas, half_lens)
+        t = np.ascontiguousarray(t, dtype=np.float64)
+        half = np.ascontiguousarray(half, dtype=np.int32)
+        off = np.ascontiguousarray(off, dtype=np.int32)
+        ws = _workspace(OP_FIR_LAPLACIAN_MFMA, H, W, S, x.device, workspace)
+        _check(lib().fdvm_fir_laplacian_mfma(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(),
+                                             out.stride(1), out.stride(0),
+                                             t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             half.ctypes.data_as(ip), off.ctypes.data_as(ip), sig, S,
+                                             BOUNDARIES[boundary], ws.data_ptr(), ws.numel(),
+                                             _stream_ptr(x.device)), "fdvm_fir_laplacian_mfma")
+        return out
+    if algo != FIR_DIRECT:
+        raise ValueError("fir_laplacian: algo FIR_DIRECT or FIR_TOEPLITZ_MFMA_HALF")
+    taps, half, off = fir_taps_device(kind, sigmas, half_lens, x.device)
+    ws = _workspace(OP_FIR_LAPLACIAN, H, W, S, x.device, workspace)
     _check(lib().fdvm_fir_laplacian(x.data_ptr(), _dtype_code(x), H, W, x.stride(0), out.data_ptr(), out.stride(1),
                                     out.stride(0), taps.data_ptr(), half.ctypes.data_as(ip), off.ctypes.data_as(ip),
                                     sig, S, BOUNDARIES[boundary], ws.data_ptr(), ws.numel(), _stream_ptr(x.device)),

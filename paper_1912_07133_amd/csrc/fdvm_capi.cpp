@@ -181,6 +181,7 @@ size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_h
         case FDVM_OP_FIR_LAPLACIAN: return fir_laplacian_workspace_bytes(H, W);
         case FDVM_OP_IIR_LAPLACIAN_BACKWARD: return iir_backward_workspace_bytes(H, W, nscales);
         case FDVM_OP_FIR_LAPLACIAN_BACKWARD: return fir_backward_workspace_bytes(H, W, nscales);
+        case FDVM_OP_FIR_LAPLACIAN_MFMA: return fir_laplacian_mfma_workspace_bytes(H, W, nscales);
         case FDVM_OP_IIR_HESSIAN:
             return (((size_t)H * W * sizeof(int32_t) + 255) & ~(size_t)255) * nscales +
                    iir_cols_workspace_bytes(H, W, nscales, 3) + iir_rexp_bytes(H) +
@@ -494,6 +495,33 @@ fdvm_status fdvm_fir_laplacian(const void *in, fdvm_dtype dt, int64_t H, int64_t
     if (ws_bytes < fir_laplacian_workspace_bytes(H, W)) return FDVM_ENOMEM;
     return from_hip(launch_fir_laplacian(in, dt, H, W, in_pitch, out, out_pitch, plane_stride, taps_dev, half_len,
                                          tap_offset, sigmas, nscales, bc, ws, static_cast<hipStream_t>(stream)));
+}
+
+fdvm_status fdvm_fir_laplacian_mfma(const void *in, fdvm_dtype dt, int64_t H, int64_t W, int64_t in_pitch,
+                                    float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                                    const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                                    int nscales, fdvm_boundary bc, void *ws, size_t ws_bytes, void *stream) {
+    fdvm_status st = check_image(in, H, W, in_pitch);
+    if (st != FDVM_OK) return st;
+    st = check_planes(out, H, W, out_pitch, plane_stride, nscales);
+    if (st != FDVM_OK) return st;
+    if (dt != FDVM_U16 && dt != FDVM_F16 && dt != FDVM_BF16) return FDVM_EINVAL;
+    if (bc != FDVM_BC_REPLICATE && bc != FDVM_BC_ZERO) return FDVM_EINVAL;
+    if (!taps || !half_len || !tap_offset || !sigmas || !ws) return FDVM_EINVAL;
+    for (int s = 0; s < nscales; ++s) {
+        if (half_len[s] < 1 || half_len[s] > FDVM_MAX_FIR_LAP_MFMA_HALF) return FDVM_ERANGE;
+        if (tap_offset[s] < 0) return FDVM_EINVAL;
+        if (!finite_pos(sigmas[s])) return FDVM_ERANGE;
+        const double *h = taps + tap_offset[s];
+        const int K = half_len[s];
+        for (int m = 1; m <= K; ++m)
+            if (h[K + m] != h[K - m]) return FDVM_EINVAL;  // symmetric taps only
+    }
+    if (ws_bytes < fir_laplacian_mfma_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
+    if (!fir_mfma_available()) return FDVM_EUNSUPPORTED;
+    return from_hip(launch_fir_laplacian_mfma(in, dt, H, W, in_pitch, ws, out, out_pitch, plane_stride, taps,
+                                              half_len, tap_offset, sigmas, nscales, bc,
+                                              static_cast<hipStream_t>(stream)));
 }
 
 fdvm_status fdvm_highpass(const float *blur, int64_t H, int64_t W, int64_t pitch, int64_t plane_stride,

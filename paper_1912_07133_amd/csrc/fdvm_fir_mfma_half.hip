@@ -178,7 +178,7 @@ __global__ __launch_bounds__(256) void fir_half_tables_kernel(u32x4 *__restrict_
 // around a load, so the loads of later groups stay in flight.  Logical blocks
 // (scale, row tile within a group of HT_RG, position group, row-tile group),
 // scale fastest, XCD-contiguous.
-template <typename H, int SRC, bool OUT_F32, bool FAST>
+template <typename H, int SRC, bool OUT_F32, bool FAST, bool ACCUM = false>
 __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     const uint16_t *__restrict__ src, const uint16_t *__restrict__ src_lo, int64_t src_pitch, int64_t src_plane,
     int R, int n, int n_in, void *__restrict__ dst, uint16_t *__restrict__ dst_lo, int64_t dst_pitch,
@@ -511,11 +511,14 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
                     const int y = y0 + 4 * lq;
                     float *o = static_cast<float *>(dst) + base + y;
                     if (vec_out && y + 3 < R_out) {
+                        if constexpr (ACCUM)
+                            w = __builtin_bit_cast(u32x4, *reinterpret_cast<const f32x4 *>(o) +
+                                                              __builtin_bit_cast(f32x4, w));
                         *reinterpret_cast<u32x4 *>(o) = w;
                     } else {
 #pragma unroll
                         for (int u = 0; u < 4; ++u)
-                            if (y + u < R_out) o[u] = __uint_as_float(w[u]);
+                            if (y + u < R_out) o[u] = (ACCUM ? o[u] : 0.0f) + __uint_as_float(w[u]);
                     }
                 } else {
                     if (k & 1) w = u32x4{w[2], w[3], w[0], w[1]};
@@ -548,11 +551,13 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
             if constexpr (OUT_F32) {
                 float *o = static_cast<float *>(dst) + base + y;
                 if (vec_out && y + 3 < R_out) {
-                    *reinterpret_cast<f32x4 *>(o) = f32x4{v[0], v[1], v[2], v[3]};
+                    f32x4 a = f32x4{v[0], v[1], v[2], v[3]};
+                    if constexpr (ACCUM) a += *reinterpret_cast<const f32x4 *>(o);
+                    *reinterpret_cast<f32x4 *>(o) = a;
                 } else {
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        if (y + u < R_out) o[u] = v[u];
+                        if (y + u < R_out) o[u] = (ACCUM ? o[u] : 0.0f) + v[u];
                 }
             } else {
                 uint16_t hi[4], lo[4];
@@ -578,7 +583,7 @@ __global__ __launch_bounds__(HT_WPB * 64) void fir_half_rows_kernel(
     }
 }
 
-template <typename H, int SRC, bool OUT_F32, bool FAST>
+template <typename H, int SRC, bool OUT_F32, bool FAST, bool ACCUM = false>
 hipError_t rows_pass(const void *src, const void *src_lo, int64_t src_pitch, int64_t src_plane, int64_t R,
                      int64_t n, int64_t n_in, void *dst, void *dst_lo, int64_t dst_pitch, int64_t dst_plane,
                      int64_t R_out, int boundary, bool vec_out, const u32x4 *tables, const HalfSet &hs, int kp_max,
@@ -589,7 +594,7 @@ hipError_t rows_pass(const void *src, const void *src_lo, int64_t src_pitch, int
     const int stage_off = ((2 * table_entries(kp_max) + HT_WPB * 64 - 1) / (HT_WPB * 64)) * (HT_WPB * 64);
     const int stage = FAST ? HT_WPB * (SRC == SRC_PAIR ? 512 : 256) : 0;   // 16-byte entries
     const size_t lds = sizeof(u32x4) * (size_t)(stage_off + stage);
-    hipLaunchKernelGGL((fir_half_rows_kernel<H, SRC, OUT_F32, FAST>), dim3(nrt * npg * (unsigned)hs.nscales),
+    hipLaunchKernelGGL((fir_half_rows_kernel<H, SRC, OUT_F32, FAST, ACCUM>), dim3(nrt * npg * (unsigned)hs.nscales),
                        dim3(HT_WPB * 64), lds, st, static_cast<const uint16_t *>(src),
                        static_cast<const uint16_t *>(src_lo), src_pitch, src_plane, (int)R, (int)n, (int)n_in, dst,
                        static_cast<uint16_t *>(dst_lo), dst_pitch, dst_plane, (int)R_out, boundary, (int)vec_out,
@@ -640,6 +645,239 @@ hipError_t run_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch, boo
                                               W, boundary, vec_out, tables, hs, kp_max, st);
 }
 
+
+// ---------------------------------------------------------------- detection
+// response on the matrix cores.  With d = h * [1, -2, 1] (Table I, d = 2),
+// sigma^2 (D20 + D02) of the separable blur is sigma^2 (h_y (d_x x) +
+// d_y (h_x x)): pass 1 filters the rows with h and with d (two tap sets per
+// scale, both of half-length K + 1), pass 2 filters the columns of the
+// h-plane with d and then, accumulating, those of the d-plane with h.  No
+// blur is formed, so none is rounded before the differences.  The
+// difference taps sum to zero and are small (about 1 / sigma^2 of h): the
+// d-plane is stored times 2^(e_h - e_d) (the exponents of the two tap sets'
+// largest magnitudes), so that it spans the h-plane's range and both pass-2
+// products carry the same factor.  The second differences of the oracle
+// clamp the blur at the image edge, where these filters see the extension:
+// the first and last rows and columns are corrected afterwards in float64
+// (lap_rows_fix_kernel, lap_edge_sums_kernel, lap_cols_fix_kernel).
+
+constexpr int LAP_MAX = FDVM_MAX_SCALES / 2;   // scales per launch (two tap sets each)
+constexpr int LAP_TAPS = HT_ARG_TAPS / 2;
+
+struct LapFix {   // the blur taps h(0..K) of a launch's scales, float32, and sigma^2
+    int q;
+    int K[LAP_MAX];
+    int off[LAP_MAX];
+    float sig2[LAP_MAX];
+    float h[LAP_TAPS];
+};
+
+__device__ __forceinline__ float tap_of(const LapFix &f, int s, int m) {
+    const int a = m < 0 ? -m : m;
+    return a <= f.K[s] ? f.h[f.off[s] + a] : 0.0f;
+}
+
+// The edge terms.  With B = h * P_ext (P extended by the boundary rule), the
+// clamped difference at the first sample wants B(0) where the filters used
+// B(-1): B(0) - B(-1) = sum_m h(m) [P_ext(-m) - P_ext(-1 - m)], whose terms
+// with both indices outside vanish, leaving
+//     e_first = [zero extension] h(0) P(0) + sum_{j=1..K} h(j) (P_ext(j) - P_ext(j - 1)),
+// and the mirror image at the last sample.  One wavefront per line, lanes
+// striding along it (coalesced), a butterfly sum at the end.
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// e_first and e_last of one line of n samples, get(j) the sample j in [0, n)
+template <typename G>
+__device__ __forceinline__ void edge_terms(const LapFix &f, int s, int n, bool rep, G get, double &first,
+                                           double &last) {
+    const int K = f.K[s];
+    const int lane = threadIdx.x & 63;
+    const double p0 = get(0), pn = get(n - 1);
+    auto ext = [&](int j, double inside_edge) { return j < n ? get(j) : (rep ? inside_edge : 0.0); };
+    double a = 0.0, b = 0.0;
+    for (int j = 1 + lane; j <= K; j += 64) {
+        const double h = f.h[f.off[s] + j];
+        a += h * (ext(j, pn) - ext(j - 1, pn));
+        // mirror: P_ext(n - 1 - j) - P_ext(n - j), indices below 0 extended by P(0)
+        const int i1 = n - 1 - j, i0 = n - j;
+        const double v1 = i1 >= 0 ? get(i1) : (rep ? p0 : 0.0);
+        const double v0 = i0 >= 0 ? get(i0) : (rep ? p0 : 0.0);
+        b += h * (v1 - v0);
+    }
+    first = wave_sum_d(a);
+    last = wave_sum_d(b);
+    if (!rep) {
+        first += (double)f.h[f.off[s]] * p0;
+        last += (double)f.h[f.off[s]] * pn;
+    }
+}
+
+// the D02 term at the first and last rows: e from the h-plane of pass 1
+// (row x, samples along y), V(0, x) += sigma^2 e_first, V(H - 1, x) += sigma^2 e_last
+template <typename T>
+__global__ __launch_bounds__(256) void lap_rows_fix_kernel(const uint16_t *__restrict__ ph,
+                                                           const uint16_t *__restrict__ pl, int64_t hp, int W, int H,
+                                                           int boundary, float inv_mid, LapFix f, float *out,
+                                                           int64_t out_pitch, int64_t plane_stride) {
+    const int x = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = blockIdx.y;
+    if (x >= W) return;
+    const int64_t row = ((int64_t)(2 * s) * W + x) * hp;   // the h-plane of scale s
+    auto get = [&](int j) -> double {
+        return ((double)Op<T>::value(ph[row + j]) + (double)Op<T>::value(pl[row + j]) / Op<T>::lo_scale) *
+               inv_mid;
+    };
+    double first, last;
+    edge_terms(f, s, H, boundary == FDVM_BC_REPLICATE, get, first, last);
+    if ((threadIdx.x & 63) != 0) return;
+    float *o = out + (int64_t)s * plane_stride + x;
+    const double sg = f.sig2[s];
+    if (H == 1) {
+        o[0] += (float)(sg * (first + last));
+    } else {
+        o[0] += (float)(sg * first);
+        o[(int64_t)(H - 1) * out_pitch] += (float)(sg * last);
+    }
+}
+
+template <typename TIn>
+__device__ __forceinline__ double sample_at(const TIn *p) {
+    if constexpr (std::is_same_v<TIn, uint16_t>)
+        return (double)*p;
+    else
+        return (double)Op<TIn>::value(*reinterpret_cast<const uint16_t *>(p));
+}
+
+// the D20 term's row values: e_first and e_last of every frame row (the row
+// filter's value at the edge column minus one column outside), per scale
+template <typename TIn>
+__global__ __launch_bounds__(256) void lap_edge_sums_kernel(const TIn *__restrict__ in, int64_t in_pitch, int W,
+                                                            int H, int boundary, LapFix f, double *__restrict__ c) {
+    const int y = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int s = blockIdx.y;
+    if (y >= H) return;
+    const TIn *r = in + (int64_t)y * in_pitch;
+    double first, last;
+    edge_terms(f, s, W, boundary == FDVM_BC_REPLICATE, [&](int j) { return sample_at<TIn>(r + j); }, first, last);
+    if ((threadIdx.x & 63) != 0) return;
+    c[((int64_t)s * 2) * H + y] = first;
+    c[((int64_t)s * 2 + 1) * H + y] = last;
+}
+
+// V(y, 0) += sigma^2 (h_y * c_first)(y), V(y, W - 1) += sigma^2 (h_y * c_last)(y),
+// c extended along y by the boundary rule; each block filters 256 rows from
+// a window of both columns staged in LDS
+constexpr int LAP_FIX_ROWS = 256;
+__global__ __launch_bounds__(LAP_FIX_ROWS) void lap_cols_fix_kernel(const double *__restrict__ c, int W, int H,
+                                                                    int boundary, LapFix f, float *out,
+                                                                    int64_t out_pitch, int64_t plane_stride) {
+    __shared__ double win[2][LAP_FIX_ROWS + 2 * FDVM_MAX_FIR_LAP_MFMA_HALF];
+    const int s = blockIdx.y;
+    const int y0 = blockIdx.x * LAP_FIX_ROWS;
+    const int K = f.K[s];
+    const bool rep = boundary == FDVM_BC_REPLICATE;
+    const double *cl = c + ((int64_t)s * 2) * H;
+    const double *cr = cl + H;
+    for (int i = threadIdx.x; i < LAP_FIX_ROWS + 2 * K; i += LAP_FIX_ROWS) {
+        int j = y0 - K + i;
+        const bool in = j >= 0 && j < H;
+        j = min(max(j, 0), H - 1);
+        win[0][i] = (in || rep) ? cl[j] : 0.0;
+        win[1][i] = (in || rep) ? cr[j] : 0.0;
+    }
+    __syncthreads();
+    const int y = y0 + threadIdx.x;
+    if (y >= H) return;
+    double lft = 0.0, rgt = 0.0;
+    for (int m = -K; m <= K; ++m) {
+        const double h = f.h[f.off[s] + (m < 0 ? -m : m)];
+        lft += h * win[0][threadIdx.x + K - m];
+        rgt += h * win[1][threadIdx.x + K - m];
+    }
+    float *o = out + (int64_t)s * plane_stride + (int64_t)y * out_pitch;
+    const double sg = f.sig2[s];
+    if (W == 1) {
+        o[0] += (float)(sg * (lft + rgt));
+    } else {
+        o[0] += (float)(sg * lft);
+        o[W - 1] += (float)(sg * rgt);
+    }
+}
+
+// one launch's scales: ht holds h_s (entry 2 s) and d_s (entry 2 s + 1)
+template <typename T, int SRC1, typename TIn>
+hipError_t run_lap_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch, bool vec_in, void *ws, float *out,
+                         int64_t out_pitch, int64_t plane_stride, bool vec_out, const HalfTaps &ht,
+                         const float *unscale, const LapFix &fx, int boundary, hipStream_t st) {
+    constexpr float mid = std::is_same_v<T, _Float16> ? 0.0625f : 1.0f;
+    const int q = fx.q;
+    u32x4 *tables = static_cast<u32x4 *>(ws);
+    const int64_t hp = pair_pitch(H);
+    uint16_t *ph = reinterpret_cast<uint16_t *>(static_cast<char *>(ws) + HT_TABLE_BYTES);
+    uint16_t *pl = ph + (int64_t)2 * q * W * hp;
+    double *cb = reinterpret_cast<double *>(pl + (int64_t)2 * q * W * hp);
+    int kp_max = 0;
+    for (int e = 0; e < 2 * q; ++e) kp_max = std::max(kp_max, round_kp(ht.K[e]));
+    hipLaunchKernelGGL(fir_half_tables_kernel<T>, dim3(2 * q), dim3(256), 0, st, tables, ht);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // pass 1: both tap sets, each plane in the h set's units (the d set is
+    // scaled by 2^-e_d in its table, so 2^e_h leaves the d-plane times
+    // 2^(e_h - e_d))
+    HalfSet h1{};
+    h1.nscales = 2 * q;
+    for (int j = 0; j < 2 * q; ++j) {
+        h1.K[j] = ht.K[j];
+        h1.tab[j] = ht.tab[j];
+        h1.post[j] = unscale[2 * (j / 2)] * mid;
+    }
+    if (vec_in && W % 8 == 0)
+        e = rows_pass<T, SRC1, false, true>(in, nullptr, in_pitch, 0, H, W, W, ph, pl, hp, W * hp, hp, boundary, true,
+                                            tables, h1, kp_max, st);
+    else
+        e = rows_pass<T, SRC1, false, false>(in, nullptr, in_pitch, 0, H, W, W, ph, pl, hp, W * hp, hp, boundary,
+                                             true, tables, h1, kp_max, st);
+    if (e != hipSuccess) return e;
+    // pass 2: the h-planes' columns with d, then the d-planes' columns with h,
+    // both products scaled by sigma^2 2^e_d / mid
+    HalfSet h2{};
+    h2.nscales = q;
+    for (int j = 0; j < q; ++j) {
+        h2.K[j] = ht.K[2 * j + 1];
+        h2.tab[j] = ht.tab[2 * j + 1];
+        h2.post[j] = fx.sig2[j] * unscale[2 * j + 1] / mid;
+    }
+    const int64_t pstride = 2 * W * hp;   // every other plane
+    e = rows_pass<T, SRC_PAIR, true, true, false>(ph, pl, hp, pstride, W, H, hp, out, nullptr, out_pitch,
+                                                 plane_stride, W, boundary, vec_out, tables, h2, kp_max, st);
+    if (e != hipSuccess) return e;
+    for (int j = 0; j < q; ++j) {
+        h2.K[j] = ht.K[2 * j];
+        h2.tab[j] = ht.tab[2 * j];
+    }
+    e = rows_pass<T, SRC_PAIR, true, true, true>(ph + W * hp, pl + W * hp, hp, pstride, W, H, hp, out, nullptr,
+                                                out_pitch, plane_stride, W, boundary, vec_out, tables, h2, kp_max,
+                                                st);
+    if (e != hipSuccess) return e;
+    // the edge rows and columns, in float64
+    hipLaunchKernelGGL(lap_rows_fix_kernel<T>, dim3((unsigned)((W + 3) / 4), (unsigned)q), dim3(256), 0, st, ph,
+                       pl, hp, (int)W, (int)H, boundary, 1.0f / mid, fx, out, out_pitch, plane_stride);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lap_edge_sums_kernel<TIn>, dim3((unsigned)((H + 3) / 4), (unsigned)q), dim3(256), 0, st,
+                       static_cast<const TIn *>(in), in_pitch, (int)W, (int)H, boundary, fx, cb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(lap_cols_fix_kernel, dim3((unsigned)((H + LAP_FIX_ROWS - 1) / LAP_FIX_ROWS), (unsigned)q),
+                       dim3(LAP_FIX_ROWS), 0, st, cb,
+                       (int)W, (int)H, boundary, fx, out, out_pitch, plane_stride);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t fir_mfma_half_workspace_bytes(int64_t H, int64_t W, int nscales) {
@@ -688,6 +926,81 @@ hipError_t launch_fir_mfma_half(const void *in, int dtype, int64_t H, int64_t W,
         else
             e = run_chunk<__bf16, SRC_HALF>(in, H, W, in_pitch, vec_in, ws, o, out_pitch, plane_stride, vec_out,
                                             ht, unscale, boundary, st);
+        if (e != hipSuccess) return e;
+        s0 += q;
+    }
+    return hipSuccess;
+}
+
+
+size_t fir_laplacian_mfma_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    const int q = std::min(nscales, LAP_MAX);
+    return HT_TABLE_BYTES + (size_t)2 * q * (size_t)W * (size_t)pair_pitch(H) * 4 +
+           (size_t)2 * q * (size_t)H * sizeof(double);
+}
+
+hipError_t launch_fir_laplacian_mfma(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, void *ws,
+                                     float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                                     const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                                     int nscales, int boundary, hipStream_t st) {
+    if (dtype != FDVM_F16 && dtype != FDVM_BF16 && dtype != FDVM_U16) return hipErrorInvalidValue;
+    const bool vec_in = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && ((in_pitch * 2) % 16 == 0);
+    for (int s0 = 0; s0 < nscales;) {
+        // the longest run of scales whose two tap sets fit the builders' arguments
+        HalfTaps ht{};
+        LapFix fx{};
+        float unscale[FDVM_MAX_SCALES];
+        int pos = 0, fpos = 0, tab = 0, q = 0;
+        while (s0 + q < nscales && q < LAP_MAX && pos + 2 * (half_len[s0 + q] + 2) <= HT_ARG_TAPS &&
+               fpos + half_len[s0 + q] + 1 <= LAP_TAPS) {
+            const int K = half_len[s0 + q];
+            const double *hd = taps + tap_offset[s0 + q] + K;   // h(m) = hd[m], |m| <= K
+            auto hv = [&](int m) { return (m < -K || m > K) ? 0.0 : hd[m]; };
+            double hm = 0.0, dm = 0.0;
+            for (int m = 0; m <= K + 1; ++m) {
+                hm = std::fmax(hm, std::fabs(hv(m)));
+                dm = std::fmax(dm, std::fabs(hv(m - 1) - 2.0 * hv(m) + hv(m + 1)));
+            }
+            int eh = 0, ed = 0;
+            if (hm > 0.0) std::frexp(hm, &eh);
+            if (dm > 0.0) std::frexp(dm, &ed);
+            for (int t = 0; t < 2; ++t) {   // entry 2 q: h (padded to K + 1), 2 q + 1: d
+                const int ent = 2 * q + t;
+                const int ex = t ? ed : eh;
+                unscale[ent] = std::ldexp(1.0f, ex);
+                ht.K[ent] = K + 1;
+                ht.off[ent] = pos;
+                ht.tab[ent] = tab;
+                for (int m = 0; m <= K + 1; ++m) {
+                    const double v = t ? hv(m - 1) - 2.0 * hv(m) + hv(m + 1) : hv(m);
+                    ht.h[pos + m] = (float)std::ldexp(v, -ex);
+                }
+                pos += K + 2;
+                tab += 2 * table_entries(round_kp(K + 1));
+            }
+            fx.K[q] = K;
+            fx.off[q] = fpos;
+            fx.sig2[q] = (float)(sigmas[s0 + q] * sigmas[s0 + q]);
+            for (int m = 0; m <= K; ++m) fx.h[fpos + m] = (float)hd[m];
+            fpos += K + 1;
+            ++q;
+        }
+        if (q == 0) return hipErrorInvalidValue;
+        ht.nscales = 2 * q;
+        fx.q = q;
+        float *o = out + (int64_t)s0 * plane_stride;
+        const bool vec_out = (reinterpret_cast<uintptr_t>(o) % 16 == 0) && (out_pitch % 4 == 0) &&
+                             (plane_stride % 4 == 0);
+        hipError_t e;
+        if (dtype == FDVM_F16)
+            e = run_lap_chunk<_Float16, SRC_HALF, _Float16>(in, H, W, in_pitch, vec_in, ws, o, out_pitch,
+                                                            plane_stride, vec_out, ht, unscale, fx, boundary, st);
+        else if (dtype == FDVM_U16)
+            e = run_lap_chunk<_Float16, SRC_U16, uint16_t>(in, H, W, in_pitch, vec_in, ws, o, out_pitch,
+                                                           plane_stride, vec_out, ht, unscale, fx, boundary, st);
+        else
+            e = run_lap_chunk<__bf16, SRC_HALF, __bf16>(in, H, W, in_pitch, vec_in, ws, o, out_pitch, plane_stride,
+                                                        vec_out, ht, unscale, fx, boundary, st);
         if (e != hipSuccess) return e;
         s0 += q;
     }

@@ -173,6 +173,16 @@ hipError_t launch_fir_mfma_half(const void *in, int dtype, int64_t H, int64_t W,
                                 float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
                                 const int32_t *half_len, const int32_t *tap_offset, int nscales, int boundary,
                                 hipStream_t stream);
+// The FIR detection response on the matrix cores (half-precision operand
+// pairs): both row filters (h, d = h * [1, -2, 1]) in one launch, both column
+// filters into V (the second accumulating), the edge rows and columns
+// corrected in float64.  Workspace: tap tables, 2 S transposed pair planes
+// (at most FDVM_MAX_SCALES / 2 scales per launch), 2 S H edge sums.
+size_t fir_laplacian_mfma_workspace_bytes(int64_t H, int64_t W, int nscales);
+hipError_t launch_fir_laplacian_mfma(const void *in, int dtype, int64_t H, int64_t W, int64_t in_pitch, void *ws,
+                                     float *out, int64_t out_pitch, int64_t plane_stride, const double *taps,
+                                     const int32_t *half_len, const int32_t *tap_offset, const double *sigmas,
+                                     int nscales, int boundary, hipStream_t stream);
 size_t fir_workspace_bytes(int64_t H, int64_t W, int nscales, int max_half);
 // One direct FIR pass along x (axis 0, frame of any input type) or y (axis 1,
 // float32 input): out (+)= sum_m h(|m|) in_ext(n - m), h = h(0..K) (float64,

@@ -146,6 +146,34 @@ def test_device_calls_validate_on_the_host():
                            None) == P.EINVAL
 
 
+def test_fir_laplacian_mfma_validation():
+    """fdvm_fir_laplacian_mfma rejects, on the host, float32 frames,
+    asymmetric taps, half-lengths beyond FDVM_MAX_FIR_LAP_MFMA_HALF, bad sigmas
+    and short workspaces (fake device pointers, nothing is launched)."""
+    L = P.lib()
+    fake = ctypes.c_void_p(0x1000)
+    half = (ctypes.c_int32 * 1)(2)
+    off = (ctypes.c_int32 * 1)(0)
+    sym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.1)
+    asym = (ctypes.c_double * 5)(0.1, 0.2, 0.4, 0.2, 0.11)
+    sig = (ctypes.c_double * 1)(2.0)
+    big = 1 << 30
+
+    def call(dt, taps=sym, hl=half, sg=sig, ws_bytes=big, bc=0):
+        return L.fdvm_fir_laplacian_mfma(fake, dt, 8, 8, 8, fake, 8, 64, taps, hl, off, sg, 1, bc, fake, ws_bytes,
+                                         None)
+
+    assert call(P.F32) == P.EINVAL
+    assert call(P.F16, taps=asym) == P.EINVAL
+    assert call(P.F16, hl=(ctypes.c_int32 * 1)(P.MAX_FIR_LAP_MFMA_HALF + 1)) == P.ERANGE
+    assert call(P.F16, hl=(ctypes.c_int32 * 1)(0)) == P.ERANGE
+    assert call(P.U16, sg=(ctypes.c_double * 1)(-1.0)) == P.ERANGE
+    assert call(P.BF16, bc=7) == P.EINVAL
+    need = P.workspace_bytes(P.OP_FIR_LAPLACIAN_MFMA, 8, 8, 1)
+    assert need > 0
+    assert call(P.F16, ws_bytes=need - 1) == P.ENOMEM
+
+
 def test_workspace_sizes():
     assert P.workspace_bytes(P.OP_BLUR_IIR, 2048, 2048, 8) >= 8 * 32 * 6 * 2048 * 4
     assert P.workspace_bytes(P.OP_IIR_LAPLACIAN, 2048, 2048, 8) >= 8 * 2048 * 2048 * 4
