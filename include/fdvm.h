@@ -433,9 +433,9 @@ enum { FDVM_OP_BLUR_IIR = 0, FDVM_OP_BLUR_FIR = 1, FDVM_OP_DETECT = 2, FDVM_OP_I
  * scales and maximum FIR half-length max_half_len (0 if unused). */
 size_t fdvm_workspace_bytes(int op, int64_t H, int64_t W, int nscales, int max_half_len);
 
-/* Largest FIR half-length of fdvm_fir_laplacian_mfma: both tap sets of a
- * scale (K + 2 coefficients each) must fit one launch's argument table. */
-#define FDVM_MAX_FIR_LAP_MFMA_HALF 438
+/* Largest FIR half-length of fdvm_fir_laplacian_mfma: the difference taps
+ * reach K + 1, which must fit the matrix-core tap tables (512 at most). */
+#define FDVM_MAX_FIR_LAP_MFMA_HALF 511
 
 /*
  * fdvm_fir_laplacian_mfma -- the FIR detection response of

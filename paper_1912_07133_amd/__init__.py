@@ -36,7 +36,7 @@ FIR_DIRECT, FIR_TOEPLITZ_MFMA, FIR_TOEPLITZ_MFMA_HALF = 0, 1, 2
 HP_LAPLACIAN, HP_D20, HP_D02, HP_D11, HP_D10, HP_D01 = 1, 2, 4, 8, 16, 32
 (OP_BLUR_IIR, OP_BLUR_FIR, OP_DETECT, OP_IIR_LAPLACIAN, OP_BLUR_IIR_ADJOINT, OP_PLANE_DOTS, OP_IIR_HESSIAN,
  OP_FIR_LAPLACIAN, OP_IIR_LAPLACIAN_BACKWARD, OP_FIR_LAPLACIAN_BACKWARD, OP_FIR_LAPLACIAN_MFMA) = range(11)
-MAX_FIR_LAP_MFMA_HALF = 438
+MAX_FIR_LAP_MFMA_HALF = 511
 GRAD_X, GRAD_SIGMA = 1, 2
 MAX_SCALES = 16
 MAX_FIR_HALF = 512

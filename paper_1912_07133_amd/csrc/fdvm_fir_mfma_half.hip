@@ -662,7 +662,7 @@ hipError_t run_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch, boo
 // (lap_rows_fix_kernel, lap_edge_sums_kernel, lap_cols_fix_kernel).
 
 constexpr int LAP_MAX = FDVM_MAX_SCALES / 2;   // scales per launch (two tap sets each)
-constexpr int LAP_TAPS = HT_ARG_TAPS / 2;
+constexpr int LAP_TAPS = HT_ARG_TAPS;   // the edge kernels' copy of h(0..K), all scales of a launch
 
 struct LapFix {   // the blur taps h(0..K) of a launch's scales, float32, and sigma^2
     int q;
@@ -808,11 +808,22 @@ __global__ __launch_bounds__(LAP_FIX_ROWS) void lap_cols_fix_kernel(const double
     }
 }
 
-// one launch's scales: ht holds h_s (entry 2 s) and d_s (entry 2 s + 1)
+// one launch's scales: tap set 2 s is h_s, 2 s + 1 is d_s (half-length K_s + 1
+// both); their tables are built by one or more builder launches (each within
+// the builder's argument table)
+struct LapPlan {
+    int q;
+    int K[2 * LAP_MAX];
+    int tab[2 * LAP_MAX];
+    float unscale[2 * LAP_MAX];
+    int nbatch;
+    HalfTaps batch[2 * LAP_MAX];
+};
+
 template <typename T, int SRC1, typename TIn>
 hipError_t run_lap_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch, bool vec_in, void *ws, float *out,
-                         int64_t out_pitch, int64_t plane_stride, bool vec_out, const HalfTaps &ht,
-                         const float *unscale, const LapFix &fx, int boundary, hipStream_t st) {
+                         int64_t out_pitch, int64_t plane_stride, bool vec_out, const LapPlan &pl_,
+                         const LapFix &fx, int boundary, hipStream_t st) {
     constexpr float mid = std::is_same_v<T, _Float16> ? 0.0625f : 1.0f;
     const int q = fx.q;
     u32x4 *tables = static_cast<u32x4 *>(ws);
@@ -821,19 +832,23 @@ hipError_t run_lap_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch,
     uint16_t *pl = ph + (int64_t)2 * q * W * hp;
     double *cb = reinterpret_cast<double *>(pl + (int64_t)2 * q * W * hp);
     int kp_max = 0;
-    for (int e = 0; e < 2 * q; ++e) kp_max = std::max(kp_max, round_kp(ht.K[e]));
-    hipLaunchKernelGGL(fir_half_tables_kernel<T>, dim3(2 * q), dim3(256), 0, st, tables, ht);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    for (int e = 0; e < 2 * q; ++e) kp_max = std::max(kp_max, round_kp(pl_.K[e]));
+    hipError_t e = hipSuccess;
+    for (int b = 0; b < pl_.nbatch; ++b) {
+        hipLaunchKernelGGL(fir_half_tables_kernel<T>, dim3(pl_.batch[b].nscales), dim3(256), 0, st, tables,
+                           pl_.batch[b]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     // pass 1: both tap sets, each plane in the h set's units (the d set is
     // scaled by 2^-e_d in its table, so 2^e_h leaves the d-plane times
     // 2^(e_h - e_d))
     HalfSet h1{};
     h1.nscales = 2 * q;
     for (int j = 0; j < 2 * q; ++j) {
-        h1.K[j] = ht.K[j];
-        h1.tab[j] = ht.tab[j];
-        h1.post[j] = unscale[2 * (j / 2)] * mid;
+        h1.K[j] = pl_.K[j];
+        h1.tab[j] = pl_.tab[j];
+        h1.post[j] = pl_.unscale[2 * (j / 2)] * mid;
     }
     if (vec_in && W % 8 == 0)
         e = rows_pass<T, SRC1, false, true>(in, nullptr, in_pitch, 0, H, W, W, ph, pl, hp, W * hp, hp, boundary, true,
@@ -847,17 +862,17 @@ hipError_t run_lap_chunk(const void *in, int64_t H, int64_t W, int64_t in_pitch,
     HalfSet h2{};
     h2.nscales = q;
     for (int j = 0; j < q; ++j) {
-        h2.K[j] = ht.K[2 * j + 1];
-        h2.tab[j] = ht.tab[2 * j + 1];
-        h2.post[j] = fx.sig2[j] * unscale[2 * j + 1] / mid;
+        h2.K[j] = pl_.K[2 * j + 1];
+        h2.tab[j] = pl_.tab[2 * j + 1];
+        h2.post[j] = fx.sig2[j] * pl_.unscale[2 * j + 1] / mid;
     }
     const int64_t pstride = 2 * W * hp;   // every other plane
     e = rows_pass<T, SRC_PAIR, true, true, false>(ph, pl, hp, pstride, W, H, hp, out, nullptr, out_pitch,
                                                  plane_stride, W, boundary, vec_out, tables, h2, kp_max, st);
     if (e != hipSuccess) return e;
     for (int j = 0; j < q; ++j) {
-        h2.K[j] = ht.K[2 * j];
-        h2.tab[j] = ht.tab[2 * j];
+        h2.K[j] = pl_.K[2 * j];
+        h2.tab[j] = pl_.tab[2 * j];
     }
     e = rows_pass<T, SRC_PAIR, true, true, true>(ph + W * hp, pl + W * hp, hp, pstride, W, H, hp, out, nullptr,
                                                 out_pitch, plane_stride, W, boundary, vec_out, tables, h2, kp_max,
@@ -946,13 +961,16 @@ hipError_t launch_fir_laplacian_mfma(const void *in, int dtype, int64_t H, int64
     if (dtype != FDVM_F16 && dtype != FDVM_BF16 && dtype != FDVM_U16) return hipErrorInvalidValue;
     const bool vec_in = (reinterpret_cast<uintptr_t>(in) % 16 == 0) && ((in_pitch * 2) % 16 == 0);
     for (int s0 = 0; s0 < nscales;) {
-        // the longest run of scales whose two tap sets fit the builders' arguments
-        HalfTaps ht{};
+        // up to LAP_MAX scales per launch; their tap sets go to the table
+        // builder in batches that fit its argument table
+        static thread_local LapPlan plan;   // about 60 KB: not on the stack
+        plan = LapPlan{};
         LapFix fx{};
-        float unscale[FDVM_MAX_SCALES];
-        int pos = 0, fpos = 0, tab = 0, q = 0;
-        while (s0 + q < nscales && q < LAP_MAX && pos + 2 * (half_len[s0 + q] + 2) <= HT_ARG_TAPS &&
-               fpos + half_len[s0 + q] + 1 <= LAP_TAPS) {
+        int fpos = 0, tab = 0, q = 0;
+        HalfTaps *cur = &plan.batch[0];
+        plan.nbatch = 1;
+        int pos = 0;
+        while (s0 + q < nscales && q < LAP_MAX && fpos + half_len[s0 + q] + 1 <= LAP_TAPS) {
             const int K = half_len[s0 + q];
             const double *hd = taps + tap_offset[s0 + q] + K;   // h(m) = hd[m], |m| <= K
             auto hv = [&](int m) { return (m < -K || m > K) ? 0.0 : hd[m]; };
@@ -964,16 +982,23 @@ hipError_t launch_fir_laplacian_mfma(const void *in, int dtype, int64_t H, int64
             int eh = 0, ed = 0;
             if (hm > 0.0) std::frexp(hm, &eh);
             if (dm > 0.0) std::frexp(dm, &ed);
-            for (int t = 0; t < 2; ++t) {   // entry 2 q: h (padded to K + 1), 2 q + 1: d
+            for (int t = 0; t < 2; ++t) {   // tap set 2 q: h (padded to K + 1), 2 q + 1: d
                 const int ent = 2 * q + t;
                 const int ex = t ? ed : eh;
-                unscale[ent] = std::ldexp(1.0f, ex);
-                ht.K[ent] = K + 1;
-                ht.off[ent] = pos;
-                ht.tab[ent] = tab;
+                if (pos + K + 2 > HT_ARG_TAPS) {   // the next builder batch
+                    cur = &plan.batch[plan.nbatch++];
+                    pos = 0;
+                }
+                const int bi = cur->nscales++;
+                plan.unscale[ent] = std::ldexp(1.0f, ex);
+                plan.K[ent] = K + 1;
+                plan.tab[ent] = tab;
+                cur->K[bi] = K + 1;
+                cur->off[bi] = pos;
+                cur->tab[bi] = tab;
                 for (int m = 0; m <= K + 1; ++m) {
                     const double v = t ? hv(m - 1) - 2.0 * hv(m) + hv(m + 1) : hv(m);
-                    ht.h[pos + m] = (float)std::ldexp(v, -ex);
+                    cur->h[pos + m] = (float)std::ldexp(v, -ex);
                 }
                 pos += K + 2;
                 tab += 2 * table_entries(round_kp(K + 1));
@@ -986,7 +1011,7 @@ hipError_t launch_fir_laplacian_mfma(const void *in, int dtype, int64_t H, int64
             ++q;
         }
         if (q == 0) return hipErrorInvalidValue;
-        ht.nscales = 2 * q;
+        plan.q = q;
         fx.q = q;
         float *o = out + (int64_t)s0 * plane_stride;
         const bool vec_out = (reinterpret_cast<uintptr_t>(o) % 16 == 0) && (out_pitch % 4 == 0) &&
@@ -994,13 +1019,13 @@ hipError_t launch_fir_laplacian_mfma(const void *in, int dtype, int64_t H, int64
         hipError_t e;
         if (dtype == FDVM_F16)
             e = run_lap_chunk<_Float16, SRC_HALF, _Float16>(in, H, W, in_pitch, vec_in, ws, o, out_pitch,
-                                                            plane_stride, vec_out, ht, unscale, fx, boundary, st);
+                                                            plane_stride, vec_out, plan, fx, boundary, st);
         else if (dtype == FDVM_U16)
             e = run_lap_chunk<_Float16, SRC_U16, uint16_t>(in, H, W, in_pitch, vec_in, ws, o, out_pitch,
-                                                           plane_stride, vec_out, ht, unscale, fx, boundary, st);
+                                                           plane_stride, vec_out, plan, fx, boundary, st);
         else
             e = run_lap_chunk<__bf16, SRC_HALF, __bf16>(in, H, W, in_pitch, vec_in, ws, o, out_pitch, plane_stride,
-                                                        vec_out, ht, unscale, fx, boundary, st);
+                                                        vec_out, plan, fx, boundary, st);
         if (e != hipSuccess) return e;
         s0 += q;
     }

@@ -99,10 +99,10 @@ def test_gaussian_taps():
 
 
 def test_long_taps_and_several_launches():
-    """A half-length near the limit, a tap set that needs several launches,
-    and more scales than one launch takes."""
+    """The largest half-length, tap sets that need several table-builder
+    launches, and more scales than one launch takes."""
     x, x64 = stored("f16", 300, 1100, 11)
-    for Ks in ([430], [200, 210, 220], [4, 5, 6, 7, 8, 9, 10, 11, 12, 13]):
+    for Ks in ([511], [200, 210, 220, 400], [4, 5, 6, 7, 8, 9, 10, 11, 12, 13]):
         say(f"case: fir laplacian mfma f16 K={Ks}")
         sig = [K / 3 for K in Ks]
         V = P.fir_laplacian(x, sig, half_lens=Ks, algo=P.FIR_TOEPLITZ_MFMA_HALF).cpu().numpy()
