@@ -12,7 +12,6 @@ from __future__ import annotations
 
 import ctypes
 import functools
-import math
 import os
 import re
 from typing import Sequence
@@ -835,13 +834,7 @@ def autotune_batch(frames, sigmas: Sequence[float], tau: float, lanes=(1, 2, 4, 
     return best_nl, [chunk_of[int(f.shape[1])] for f in frames], timings
 
 
-def scale_of(sigma: float) -> float:
-    """Blob scale lambda = 2 sigma (Section 5)."""
-    return 2.0 * sigma
-
-
 __all__ = ["filter_design", "iir_designs", "iir_pass", "blur_iir", "iir_laplacian", "blur_fir", "highpass", "detect_blobs", "detect", "fir_taps",
-           "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError", "scale_of",
+           "workspace_bytes", "header_symbols", "lib", "library_available", "FdvmError",
            "Batch", "autotune_batch", "row_chunk_choices", "Frame", "blur_iir_adjoint", "laplacian_adjoint",
            "plane_dots", "dblur_dsigma_parts", "iir_laplacian_grad", "fir_laplacian_grad", "iir_hessian"]
-_ = math
