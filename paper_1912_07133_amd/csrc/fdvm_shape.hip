@@ -90,7 +90,9 @@ __device__ __forceinline__ int xcd_logical_block(int hw, int n) {
     return xcd * q + min(xcd, r) + slot;
 }
 
-constexpr int DT_NPL = 4;  // planes in each wavefront's LDS ring (the one in use + 3 in flight)
+// planes in each wavefront's LDS ring: the one awaited and the next in flight
+// (rings of 3 and 4 planes measured slower on a 2048 x 2048 x 8-scale stack)
+constexpr int DT_NPL = 2;
 
 // copy 64 lanes x 4 bytes from global memory straight into LDS (lane n to
 // l[n]); complete once vmcnt has dropped past it
@@ -116,6 +118,20 @@ __device__ __forceinline__ void read10(const uint32_t *p, uint32_t (&r)[10]) {
           "=&v"(r[8]), "=&v"(r[9])
         : "v"(a)
         : "memory");
+}
+
+// lane L of v <- the wave-uniform value u (v_writelane_b32)
+template <int L>
+__device__ __forceinline__ void write_lane(int &v, uint32_t u) {
+    asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(v) : "s"(u), "n"(L));
+}
+// f(integral_constant<int, 0>) .. f(integral_constant<int, N - 1>), in order
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
 }
 
 // Order-preserving integer key of a float32 (finite or infinite): k(a) < k(b)
@@ -186,13 +202,16 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     const int cx = min(max(x, 0), W - 1);
     uint32_t *rg = &ring[wv][0][0];
     // rows y0-1 .. y0+RB of plane min(s, S - 1) into ring slot s % DT_NPL
+    // (a wave-uniform row address plus the lane's 32-bit byte offset, which
+    // the copy takes as its scalar base and vector offset)
+    const uint32_t xoff = (uint32_t)cx * 4u;
     auto request = [&](int s) {
-        const float *P = V + (int64_t)min(s, S - 1) * plane_stride + cx;   // wave-uniform plane
+        const char *P = reinterpret_cast<const char *>(V + (int64_t)min(s, S - 1) * plane_stride);
         uint32_t *slot = rg + (s % DT_NPL) * (RB + 2) * 64;
 #pragma unroll
         for (int r = 0; r < RB + 2; ++r) {
             const int y = min(max(y0 - 1 + r, 0), H - 1);
-            row_to_lds(P + (int64_t)y * pitch, slot + r * 64);
+            row_to_lds(reinterpret_cast<const float *>(P + (int64_t)y * pitch * 4 + xoff), slot + r * 64);
         }
     };
     constexpr int AHEAD = (DT_NPL - 1) * (RB + 2);  // copies issued after the plane awaited
@@ -238,11 +257,14 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
                 rlo[r] = yin ? lo2(l, klo) : LO_NONE;
                 rhi[r] = yin ? hi2(h, khi) : HI_NONE;
             } else {
+                // the row statistics carry the threshold floors as well (as on
+                // the edge path): every decision's statistic already holds
+                // them through the centre plane, so they change no decision
                 const int kl = key_left(k), kr = key_right(k);
                 llo[r] = lo3(kl, kr, tlo);
                 lhi[r] = hi3(kl, kr, thi);
-                rlo[r] = lo3(kl, kr, k);
-                rhi[r] = hi3(kl, kr, k);
+                rlo[r] = lo2(llo[r], k);
+                rhi[r] = hi2(lhi[r], k);
             }
             if (r >= 1 && r <= RB) pl.c[r - 1] = k;
         }
@@ -270,8 +292,10 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     // condition is rebuilt through a vector register)
     const unsigned long long xmask = __builtin_amdgcn_ballot_w64(xout);
     auto decide = [&](int s, const Plane &pv, const Plane &pc, const Plane &pn) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
+        // row r's mask word goes to lane r of (whi, wlo); lanes 0..RB-1 store them
+        int wlo = 0, whi = 0;
+        static_for<RB>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
             const int y = y0 + r;
             const int lo = lo3(pc.lo8[r], pv.lo9[r], pn.lo9[r]);
             const int hi = hi3(pc.hi8[r], pv.hi9[r], pn.hi9[r]);
@@ -286,8 +310,10 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
                       (__builtin_amdgcn_ballot_w64(k >= kpos) & __builtin_amdgcn_ballot_w64(k > hi));
             }
             const unsigned long long bits = yin ? (hit & xmask) >> 1 : 0ull;   // lanes 1..62 -> bits 0..61
-            if (lane == 0) wd[s * RB + r] = bits;
-        }
+            write_lane<r>(wlo, (uint32_t)bits);
+            write_lane<r>(whi, (uint32_t)(bits >> 32));
+        });
+        if (lane < RB) wd[s * RB + lane] = ((unsigned long long)(uint32_t)whi << 32) | (uint32_t)wlo;
     };
 #pragma unroll
     for (int q = 0; q < DT_NPL; ++q) request(q);
