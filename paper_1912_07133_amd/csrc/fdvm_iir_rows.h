@@ -79,6 +79,9 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         for (int q = 0; q < R; ++q) m = fmaxf(m, rmax[wv - r + q]);
         const double bound = (double)m * a.l1;
         ex = bound > 0.0 ? 30 - ilogb(bound) : 0;
+        // |out| 2^ex <= bound 2^ex < 2^31; one step less where the bound lies
+        // within 2 of 2^31, so that no output rounds to 2^31
+        if (bound > 0.0 && ldexp(bound, ex) > 2147483646.0) --ex;
         if (row_ok && r == 0 && lane == 0) rexp[row] = ex;
     }
     float xs[C];
@@ -133,23 +136,33 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
             for (int k = 0; k < NS; ++k) sb[k] = t[k];
         }
         // ---- intra-wavefront inclusive scans (forward from the left,
-        // backward from the right): S_l <- A^(C d) S_(l-d) + S_l
+        // backward from the right): S_l <- A^(C d) S_(l-d) + S_l.  A lane
+        // with no partner d lanes away takes the zero transition instead
+        // (A^n S + S_l with p^n = 0 is S_l exactly), which is one select of
+        // p^n per direction rather than one per state.
 #pragma unroll
         for (int lvl = 0; lvl < 6; ++lvl) {
             const int d = 1 << lvl;
             const Tr tl = tr_level<K, C>(cf, lvl);
+            Tr tlf = tl, tlb = tl;
+            tlf.a = lane >= d ? tl.a : 0.0;
+            tlb.a = lane + d < 64 ? tl.a : 0.0;
+            if constexpr (K == CPAIR) {   // p^n = a + i b
+                tlf.b = lane >= d ? tl.b : 0.0;
+                tlb.b = lane + d < 64 ? tl.b : 0.0;
+            }
             double tf[NS], tb[NS];
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
                 tf[k] = __shfl_up(sf[k], d, 64);
                 tb[k] = __shfl_down(sb[k], d, 64);
             }
-            cas_advance_add<K>(tl, tf, sf);
-            cas_advance_add<K>(tl, tb, sb);
+            cas_advance_add<K>(tlf, tf, sf);
+            cas_advance_add<K>(tlb, tb, sb);
 #pragma unroll
             for (int k = 0; k < NS; ++k) {
-                if (lane >= d) sf[k] = tf[k];
-                if (lane + d < 64) sb[k] = tb[k];
+                sf[k] = tf[k];
+                sb[k] = tb[k];
             }
         }
         // ---- across the R wavefronts of the row
@@ -209,24 +222,42 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         // ---- final outputs of the chunk
         // y-(n) + b0 x(n) is kept as float32 until y+(n) is added in float64
         // (its rounding adds ~1/4 ulp to the 1/2 ulp of the stored output)
-        // (float64 throughout for the fixed-point intermediate)
+        // (float64 throughout for the fixed-point intermediate, where the
+        // output weights carry the row's 2^ex: scaling by a power of two
+        // commutes with every rounding, so the sums are those of the
+        // unscaled weights times 2^ex)
+        double wo[NS], b0o = cf.b0;
+#pragma unroll
+        for (int k = 0; k < NS; ++k) wo[k] = cf.w[k];
+        if constexpr (FX) {
+            const double sc = ldexp(1.0, ex);
+            b0o *= sc;
+#pragma unroll
+            for (int k = 0; k < NS; ++k) wo[k] *= sc;
+        }
+        auto out_of = [&](const double(&v)[NS]) {
+            double y = wo[0] * v[0];
+#pragma unroll
+            for (int k = 1; k < NS; ++k) y = fma(wo[k], v[k], y);
+            return y;
+        };
         Acc ys[C];
         if (full_wave) {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
-                ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out<K>(cf, vb));
+                ys[j] = (Acc)fma(b0o, (double)xs[j], out_of(vb));
                 cas_step<K>(cf, vb, (double)xs[j]);
             }
 #pragma unroll
             for (int j = 0; j < C; ++j) {
-                ys[j] = (Acc)((double)ys[j] + cas_out<K>(cf, vf));
+                ys[j] = (Acc)((double)ys[j] + out_of(vf));
                 cas_step<K>(cf, vf, (double)xs[j]);
             }
         } else {
 #pragma unroll
             for (int j = C - 1; j >= 0; --j) {
                 if (j < nv) {
-                    ys[j] = (Acc)fma(cf.b0, (double)xs[j], cas_out<K>(cf, vb));
+                    ys[j] = (Acc)fma(b0o, (double)xs[j], out_of(vb));
                     cas_step<K>(cf, vb, (double)xs[j]);
                 } else {
                     ys[j] = (Acc)0;
@@ -235,7 +266,7 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
 #pragma unroll
             for (int j = 0; j < C; ++j) {
                 if (j < nv) {
-                    ys[j] = (Acc)((double)ys[j] + cas_out<K>(cf, vf));
+                    ys[j] = (Acc)((double)ys[j] + out_of(vf));
                     cas_step<K>(cf, vf, (double)xs[j]);
                 }
             }
@@ -243,10 +274,16 @@ __global__ __launch_bounds__(ROW_WPB * 64) void iir_rows_kernel(
         uint32_t *dst = static_cast<uint32_t *>(out_v) + (int64_t)s * plane_stride +
                         (int64_t)(row_ok ? row : 0) * out_pitch;
         auto word = [&](int j) -> uint32_t {
-            if constexpr (FX)
-                return (uint32_t)(int)rint(ldexp((double)ys[j], ex));   // |ys 2^ex| < 2^31 by the choice of ex
-            else
+            if constexpr (FX) {
+                // rint(ys) as a two's-complement word: |ys| < 2^31 - 1 by the
+                // choice of ex, so ys + 1.5 2^52 lies in [2^52, 2^53), where the
+                // float64 spacing is 1 and the sum rounds ys to the nearest
+                // integer (ties to even); its low 32 bits are that integer
+                // modulo 2^32
+                return (uint32_t)__double2loint((double)ys[j] + 6755399441055744.0);
+            } else {
                 return __float_as_uint(ys[j]);
+            }
         };
         if (a.direct) {
             // 16-byte aligned rows.  Groups of NB = C / 4 lanes exchange their
