@@ -151,11 +151,11 @@ __device__ __forceinline__ int key_right(int k) { return __builtin_amdgcn_mov_dp
 // The planes reach LDS by direct global-to-LDS copies issued DT_NPL - 1
 // planes ahead of use; the mask words of the wavefront collect in LDS and are
 // written once at the end (no stores interleave with the counted copies).
-// Per plane and output row the kernel keeps two 3 x 3 statistics (centre
-// included) and the same without the centre; the planes rotate through three
-// register roles (previous, current, next), so the scale loop is unrolled by
-// three.  A missing plane (before the first, after the last) is a plane of
-// sentinels.
+// Per plane and output row the kernel keeps the centre and the two 3 x 3
+// statistics without it (those with it are formed where a neighbouring
+// scale's decision needs them); the planes rotate through three register
+// roles (previous, current, next), so the scale loop is unrolled by three.  A
+// missing plane (before the first, after the last) drops out of the decision.
 //
 // RAW (tau > 0): a bright candidate is negative and a dark one positive, and
 // for such a centre the float order against any neighbour is an integer order
@@ -163,7 +163,8 @@ __device__ __forceinline__ int key_right(int k) { return __builtin_amdgcn_mov_dp
 // unsigned integers (negative floats above every non-negative one, larger
 // magnitude higher); for c > 0, c > n exactly when bits(c) > bits(n) as signed
 // integers.  The statistics are then the unsigned and the signed maximum of
-// the raw bits (sentinels 0 and INT32_MIN), and no key transform is needed.
+// the raw bits, and no key transform is needed; a sample outside the image
+// enters as +0 (bits 0), which lies below both threshold floors below.
 // The thresholds join them the same way: c <= -tau exactly when bits(c) >
 // bits(-tau) - 1 unsigned, c >= tau exactly when bits(c) > bits(tau) - 1
 // signed; taken into every row's left/right maximum, they reach each
@@ -215,10 +216,13 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         }
     };
     constexpr int AHEAD = (DT_NPL - 1) * (RB + 2);  // copies issued after the plane awaited
+    // per plane and output row: the centre and the two 3 x 3 statistics
+    // without it; a neighbouring plane's 3 x 3 statistic with its centre is
+    // formed where a decision needs it (one more max per statistic there, none
+    // for it in the plane's own pass, and three planes' worth of registers less)
     struct Plane {
         int c[RB];               // centre (raw bits or key) of the output rows
-        int lo9[RB], hi9[RB];    // 3 x 3 statistics
-        int lo8[RB], hi8[RB];    // the same without the centre
+        int lo8[RB], hi8[RB];    // 3 x 3 statistics without the centre
     };
     // the two statistics of a pair / triple of values
     auto lo2 = [](int a, int b) {
@@ -245,8 +249,16 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         int rlo[RB + 2], rhi[RB + 2], llo[RB + 2], lhi[RB + 2];
 #pragma unroll
         for (int r = 0; r < RB + 2; ++r) {
-            const int k = RAW ? (int)raw[r] : fkey(__uint_as_float(raw[r]));
-            if constexpr (EDGE) {
+            int k = RAW ? (int)raw[r] : fkey(__uint_as_float(raw[r]));
+            if constexpr (EDGE && RAW) {
+                // with tau > 0 a sample outside the image can be +0 for both
+                // statistics: it is below both threshold floors, which every
+                // decision's statistics already hold, so it never changes one
+                // (and the decisions of lanes and rows outside are masked)
+                const int y = y0 - 1 + r;
+                k = (xin && y >= 0 && y < H) ? k : 0;
+            }
+            if constexpr (EDGE && !RAW) {
                 const int y = y0 - 1 + r;
                 const bool yin = y >= 0 && y < H;   // wave-uniform
                 const int klo = xin ? k : LO_NONE, khi = xin ? k : HI_NONE;
@@ -272,33 +284,48 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
         for (int r = 0; r < RB; ++r) {
             pl.lo8[r] = lo3(rlo[r], llo[r + 1], rlo[r + 2]);
             pl.hi8[r] = hi3(rhi[r], lhi[r + 1], rhi[r + 2]);
-            pl.lo9[r] = lo3(rlo[r], rlo[r + 1], rlo[r + 2]);
-            pl.hi9[r] = hi3(rhi[r], rhi[r + 1], rhi[r + 2]);
-        }
-    };
-    auto absent = [&](Plane &pl) {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            pl.lo9[r] = LO_NONE;
-            pl.hi9[r] = HI_NONE;
         }
     };
     const int kneg = fkey(-tau), kpos = fkey(tau);
     const bool xout = lane >= 1 && lane <= 62 && x < W && x >= border && x < W - border;
     unsigned long long *wd = words[wv];
-    // decisions at plane s from its neighbours in scale
-    // the decided columns as a lane mask; ballots are taken of single
+    // decisions at plane s from its neighbours in scale (a plane's 3 x 3
+    // statistic with its centre is the one without it joined with the centre:
+    // the centre row's left/right maximum already holds the threshold floor,
+    // on both paths, and a lane outside the image decides nothing).  The
+    // first plane has no plane before it; after the last plane its own
+    // 8-neighbour statistics stand in for the missing ones (the maximum of a
+    // value with itself changes nothing), so that term is dropped.
+    // The decided columns as a lane mask; ballots are taken of single
     // comparisons and combined on the scalar unit (a ballot of a combined
     // condition is rebuilt through a vector register)
     const unsigned long long xmask = __builtin_amdgcn_ballot_w64(xout);
-    auto decide = [&](int s, const Plane &pv, const Plane &pc, const Plane &pn) {
+    // lo/hi of plane s joined with plane s - 1's statistics (formed before
+    // plane s + 1's statistics, so that plane s - 1 is no longer live then)
+    auto join_prev = [&](const Plane &pv, const Plane &pc, int (&lo)[RB], int (&hi)[RB], auto has_pv) {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            lo[r] = pc.lo8[r];
+            hi[r] = pc.hi8[r];
+            if constexpr (decltype(has_pv)::value) {
+                lo[r] = lo3(lo[r], pv.lo8[r], pv.c[r]);
+                hi[r] = hi3(hi[r], pv.hi8[r], pv.c[r]);
+            }
+        }
+    };
+    auto decide = [&](int s, const int (&plo)[RB], const int (&phi)[RB], const Plane &pc, const Plane &pn,
+                      auto has_pn) {
+        constexpr bool HPN = decltype(has_pn)::value;
         // row r's mask word goes to lane r of (whi, wlo); lanes 0..RB-1 store them
         int wlo = 0, whi = 0;
         static_for<RB>([&](auto rc) {
             constexpr int r = decltype(rc)::value;
             const int y = y0 + r;
-            const int lo = lo3(pc.lo8[r], pv.lo9[r], pn.lo9[r]);
-            const int hi = hi3(pc.hi8[r], pv.hi9[r], pn.hi9[r]);
+            int lo = plo[r], hi = phi[r];
+            if constexpr (HPN) {
+                lo = lo3(lo, pn.lo8[r], pn.c[r]);
+                hi = hi3(hi, pn.hi8[r], pn.c[r]);
+            }
             const int k = pc.c[r];
             const bool yin = y < H && y >= border && y < H - border;   // wave-uniform
             // no neighbour at all (1 x 1 x 1 stack) compares as "strict" too
@@ -319,36 +346,29 @@ __global__ __launch_bounds__(DT_WAVES * 64) void detect_mask_kernel(const float 
     for (int q = 0; q < DT_NPL; ++q) request(q);
     auto run = [&](auto edge_tag) {
         Plane P0, P1, P2;
-        absent(P2);         // the plane before the first
         wait_vm<AHEAD>();   // plane 0
         stats(0, P0, edge_tag);
         // step at plane s: plane s + 1 is needed now; plane s's slot is free
-        // (its statistics are in registers).  After the last plane the centre
-        // plane's own 8-neighbour statistics stand in for the missing 3 x 3
-        // ones (the maximum of a value with itself changes nothing), so no
-        // sentinel plane is formed inside the loop.
-        auto step = [&](int s, Plane &pv, Plane &pc, Plane &pn) {
+        // (its statistics are in registers)
+        auto step = [&](int s, Plane &pv, Plane &pc, Plane &pn, auto has_pv) {
+            int plo[RB], phi[RB];
+            join_prev(pv, pc, plo, phi, has_pv);
             request(s + DT_NPL);
             wait_vm<AHEAD>();
             if (s + 1 < S) {
                 stats(s + 1, pn, edge_tag);
-                decide(s, pv, pc, pn);
+                decide(s, plo, phi, pc, pn, std::true_type{});
             } else {
-                Plane own;
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    own.lo9[r] = pc.lo8[r];
-                    own.hi9[r] = pc.hi8[r];
-                }
-                decide(s, pv, pc, own);
+                decide(s, plo, phi, pc, pn, std::false_type{});
             }
         };
-        for (int s = 0; s < S; s += 3) {
-            step(s, P2, P0, P1);
+        step(0, P2, P0, P1, std::false_type{});
+        for (int s = 1; s < S; s += 3) {
+            step(s, P0, P1, P2, std::true_type{});
             if (s + 1 >= S) break;
-            step(s + 1, P0, P1, P2);
+            step(s + 1, P1, P2, P0, std::true_type{});
             if (s + 2 >= S) break;
-            step(s + 2, P1, P2, P0);
+            step(s + 2, P2, P0, P1, std::true_type{});
         }
     };
     // a band is interior when its 64 lanes and RB + 2 rows all lie in the image
