@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, GB/s
 PMC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+EV_EVERY = 4   # timed steps per step with unit events (the units' average launch durations)
 
 
 def log(*a):
@@ -441,11 +442,22 @@ def main() -> int:
         ev[1].record(stream)
         detect_into(ev[2])
 
+    class NoEvent:
+        """stands in for the unit events of a step that is not sampled"""
+        def record(self, _stream):
+            pass
+
     def timed(step_fn, nev, steps, warmup):
+        """K steps between two events (the step rate); the units' durations
+        from HIP events around them on every EV_EVERY-th of those steps: a
+        timing event costs about 3 us on the stream, so recording three in
+        every step would add about 10 us to each step it is meant to measure"""
         for _ in range(warmup):
-            step_fn([torch.cuda.Event(enable_timing=True) for _ in range(nev)])
+            step_fn([NoEvent() for _ in range(nev)])
         torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(steps)]
+        every = EV_EVERY if steps >= 2 * EV_EVERY else 1
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] if i % every == 0
+               else [NoEvent() for _ in range(nev)] for i in range(steps)]
         start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         t_wall = time.perf_counter()
@@ -456,7 +468,8 @@ def main() -> int:
         torch.cuda.synchronize()
         wall = time.perf_counter() - t_wall
         total_ms = start.elapsed_time(stop)
-        per = [[e[i].elapsed_time(e[i + 1]) for e in evs] for i in range(nev - 1)]
+        sampled = [e for e in evs if not isinstance(e[0], NoEvent)]
+        per = [[e[i].elapsed_time(e[i + 1]) for e in sampled] for i in range(nev - 1)]
         return total_ms, wall, [float(np.mean(p)) for p in per]
 
     # ---------------- IIR path
