@@ -25,14 +25,15 @@
  *   - Device pointers are plain HIP device addresses; the caller owns every
  *     buffer (inputs, outputs, workspace).  The library allocates no device
  *     memory and keeps no pointer after returning.  Its only state: per
- *     device, FDVM_MAX_LANES internal streams and events of the batch call
- *     (created on the first multi-lane batch call on that device, under a
- *     lock) and the fixed scratch array of the no-allocation calls (its
- *     device address looked up on their first call there), both kept until
- *     the process ends.  Calls on different streams are independent, except
- *     that multi-lane batch calls that overlap on one device share those
- *     streams, and no-allocation calls that overlap on one device share that
- *     array: either must be serialised by the caller.
+ *     device, FDVM_MAX_LANES internal streams and events of the batch and
+ *     backward calls (created on the first multi-lane batch call or backward
+ *     call of several frames on that device, under a lock) and the fixed
+ *     scratch array of the no-allocation calls (its device address looked up
+ *     on their first call there), both kept until the process ends.  Calls
+ *     on different streams are independent, except that multi-lane batch
+ *     calls and backward calls of several frames that overlap on one device
+ *     share those streams, and no-allocation calls that overlap on one device
+ *     share that array: either must be serialised by the caller.
  *   - Device work is enqueued on `stream` (a hipStream_t passed as void*;
  *     NULL = the legacy default stream) and the call returns without waiting.
  *     Argument errors are detected on the host before anything is enqueued;
@@ -390,7 +391,11 @@ fdvm_status fdvm_plane_dots(const float *a, const float *b, int64_t H, int64_t W
  *            (FDVM_GRAD_SIGMA; may be NULL otherwise).
  *   ws       device workspace >= fdvm_workspace_bytes(
  *            FDVM_OP_IIR_LAPLACIAN_BACKWARD / FDVM_OP_FIR_LAPLACIAN_BACKWARD,
- *            H, W, nscales, max K), reused frame after frame.
+ *            H, W, nscales, max K).  The frames run on up to four lanes
+ *            (internal streams that wait on an event recorded on `stream`,
+ *            and on which `stream` waits in turn; frame f on lane f mod 4),
+ *            each with its own part of the workspace; the sigma gradient is
+ *            summed per lane in frame order, then over the lanes in order.
  * Errors as the forward calls; what = 0 or any other bit is FDVM_EINVAL.
  */
 enum { FDVM_GRAD_X = 1, FDVM_GRAD_SIGMA = 2 };

@@ -4,7 +4,8 @@
 //     G_s^T dL/dB_s, added in scale order (deterministic);
 //   * the assembly of dL/dsigma_s = 2/sigma_s <dL/dV_s, V_s> + <dL/dB_s,
 //     dB_s/dsigma_s> from the float64 plane inner products, summed over the
-//     frames of a batch.
+//     frames of a batch (per lane in frame order, then over the lanes in
+//     order: deterministic).
 #include "fdvm_internal.h"
 
 namespace fdvm {
@@ -39,7 +40,22 @@ __global__ __launch_bounds__(64) void gsigma_kernel(const double *__restrict__ v
     gsigma[s] = a.accumulate ? gsigma[s] + g : g;
 }
 
+// out[s] = sum over lanes l of part[l nscales + s], lanes in order
+__global__ __launch_bounds__(64) void sum_lanes_kernel(const double *__restrict__ part, int nlanes, int nscales,
+                                                       double *__restrict__ out) {
+    const int s = threadIdx.x;
+    if (s >= nscales) return;
+    double g = part[s];
+    for (int l = 1; l < nlanes; ++l) g += part[l * nscales + s];
+    out[s] = g;
+}
+
 }  // namespace
+
+hipError_t launch_sum_lanes(const double *part, int nlanes, int nscales, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(sum_lanes_kernel, dim3(1), dim3(64), 0, st, part, nlanes, nscales, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_sum_planes(const float *in, int64_t pitch, int64_t plane, int nscales, int64_t H, int64_t W,
                              float *out, int64_t out_pitch, hipStream_t st) {

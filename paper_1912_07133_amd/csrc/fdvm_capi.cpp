@@ -152,16 +152,30 @@ size_t iir_backward_inner_bytes(int64_t H, int64_t W, int nscales) {
     const size_t b = dots_workspace_bytes(H, nscales);
     return a > b ? a : b;
 }
-size_t iir_backward_workspace_bytes(int64_t H, int64_t W, int nscales) {
+size_t iir_backward_frame_bytes(int64_t H, int64_t W, int nscales) {
     return 3 * plane_bytes(H, W, nscales) + iir_backward_inner_bytes(H, W, nscales) +
            (((size_t)3 * nscales * sizeof(double) + 255) & ~(size_t)255);
 }
 // FIR backward: gB (nscales planes) | three single planes | tail table |
 // inner-product partials | 2 nscales doubles
-size_t fir_backward_workspace_bytes(int64_t H, int64_t W, int nscales) {
+size_t fir_backward_frame_bytes(int64_t H, int64_t W, int nscales) {
     return plane_bytes(H, W, nscales) + 3 * plane_bytes(H, W, 1) +
            ((((size_t)std::max(H, W)) * sizeof(double) + 255) & ~(size_t)255) + dots_workspace_bytes(H, nscales) +
            (((size_t)2 * nscales * sizeof(double) + 255) & ~(size_t)255);
+}
+// The backward calls run the frames of a batch on BWD_LANES lanes (frame f on
+// lane f mod BWD_LANES): one frame's kernels are too small to fill the GPU.
+// Workspace: one frame's part per lane, then each lane's sigma-gradient
+// partial sums (BWD_LANES x nscales doubles).
+constexpr int BWD_LANES = 4;
+size_t backward_workspace_bytes(size_t frame_bytes, int nscales) {
+    return BWD_LANES * frame_bytes + (((size_t)BWD_LANES * nscales * sizeof(double) + 255) & ~(size_t)255);
+}
+size_t iir_backward_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    return backward_workspace_bytes(iir_backward_frame_bytes(H, W, nscales), nscales);
+}
+size_t fir_backward_workspace_bytes(int64_t H, int64_t W, int nscales) {
+    return backward_workspace_bytes(fir_backward_frame_bytes(H, W, nscales), nscales);
 }
 }  // namespace
 
@@ -591,6 +605,36 @@ Lanes *lanes_for_current_device() {
     return l;
 }
 
+// Lanes 0..used-1 forked from the caller's stream with an event, and joined
+// back into it with one event per lane, also after a failure, so that a
+// capture of the caller's stream stays well formed.  With no lanes forked
+// every "lane" is the caller's stream.
+struct LaneFork {
+    hipStream_t origin;
+    Lanes *lanes = nullptr;
+    int forked = 0;
+    explicit LaneFork(hipStream_t o) : origin(o) {}
+    fdvm_status fork(int used) {
+        lanes = lanes_for_current_device();
+        if (!lanes) return FDVM_EDEVICE;
+        if (hipEventRecord(lanes->fork, origin) != hipSuccess) return FDVM_EDEVICE;
+        for (int l = 0; l < used; ++l) {
+            if (hipStreamWaitEvent(lanes->st[l], lanes->fork, 0) != hipSuccess) return join(FDVM_EDEVICE);
+            forked = l + 1;
+        }
+        return FDVM_OK;
+    }
+    hipStream_t stream(int l) const { return forked ? lanes->st[l] : origin; }
+    fdvm_status join(fdvm_status status) {
+        for (int l = 0; l < forked; ++l) {
+            if (hipEventRecord(lanes->done[l], lanes->st[l]) != hipSuccess) status = FDVM_EDEVICE;
+            else if (hipStreamWaitEvent(origin, lanes->done[l], 0) != hipSuccess) status = FDVM_EDEVICE;
+        }
+        forked = 0;
+        return status;
+    }
+};
+
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // per-lane workspace, sized for the largest frame term by term
@@ -652,31 +696,15 @@ fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_
     const LaneLayout L = lane_layout(frames, nframes, nscales, prm.order);
     const int used = std::min(nlanes, nframes);
     if (ws_bytes < L.total() * (size_t)used) return FDVM_ENOMEM;
-    hipStream_t origin = static_cast<hipStream_t>(stream);
-    Lanes *lanes = nullptr;
-    int forked = 0;  // lanes that wait on the fork event and must be joined back
-    // every lane that was forked from `origin` is joined back into it, also
-    // after a failed launch, so that a capture of `origin` stays well formed
-    auto join = [&](fdvm_status status) -> fdvm_status {
-        for (int l = 0; l < forked; ++l) {
-            if (hipEventRecord(lanes->done[l], lanes->st[l]) != hipSuccess) status = FDVM_EDEVICE;
-            else if (hipStreamWaitEvent(origin, lanes->done[l], 0) != hipSuccess) status = FDVM_EDEVICE;
-        }
-        return status;
-    };
+    LaneFork lanes(static_cast<hipStream_t>(stream));
     if (used > 1) {
-        lanes = lanes_for_current_device();
-        if (!lanes) return FDVM_EDEVICE;
-        if (hipEventRecord(lanes->fork, origin) != hipSuccess) return FDVM_EDEVICE;
-        for (int l = 0; l < used; ++l) {
-            if (hipStreamWaitEvent(lanes->st[l], lanes->fork, 0) != hipSuccess) return join(FDVM_EDEVICE);
-            forked = l + 1;
-        }
+        st = lanes.fork(used);
+        if (st != FDVM_OK) return st;
     }
     for (int f = 0; f < nframes; ++f) {
         const fdvm_frame &fr = frames[f];
         const int l = f % used;
-        hipStream_t hs = used > 1 ? lanes->st[l] : origin;
+        hipStream_t hs = lanes.stream(l);
         char *base = static_cast<char *>(ws) + L.total() * (size_t)l;
         const int64_t H = fr.H, W = fr.W;
         int32_t *mid = reinterpret_cast<int32_t *>(base);
@@ -690,9 +718,9 @@ fdvm_status fdvm_batch_detect(const fdvm_frame *frames, int nframes, const fdvm_
             e = launch_iir_cols(mid, W, mstride, rexp, V, H, W, W, H * W, true, prm, states, hs);
         if (e == hipSuccess)
             e = launch_detect(V, H, W, W, H * W, nscales, tau, border, fr.out, fr.cap, fr.count, det, hs);
-        if (e != hipSuccess) return join(FDVM_EDEVICE);
+        if (e != hipSuccess) return lanes.join(FDVM_EDEVICE);
     }
-    return join(FDVM_OK);
+    return lanes.join(FDVM_OK);
 }
 
 }  // extern "C"
@@ -758,17 +786,28 @@ extern "C" fdvm_status fdvm_iir_laplacian_backward(const void *x, fdvm_dtype dt,
         st = iir_params(df, nscales, bc, &dprm, true);
         if (st != FDVM_OK) return st;
     }
-    hipStream_t hs = static_cast<hipStream_t>(stream);
     const int64_t P = H * W;   // workspace planes: pitch W, plane H W
-    char *w = static_cast<char *>(ws);
-    float *gB = reinterpret_cast<float *>(w);
-    float *P1 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales));
-    float *P2 = reinterpret_cast<float *>(w + 2 * plane_bytes(H, W, nscales));
-    char *inner = w + 3 * plane_bytes(H, W, nscales);
-    double *res = reinterpret_cast<double *>(inner + iir_backward_inner_bytes(H, W, nscales));
+    const size_t fbytes = iir_backward_frame_bytes(H, W, nscales);
     const size_t sbytes = iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS);
+    double *gpart = reinterpret_cast<double *>(static_cast<char *>(ws) + BWD_LANES * fbytes);
+    const int used = std::min(BWD_LANES, nframes);
+    LaneFork lanes(static_cast<hipStream_t>(stream));
+    if (used > 1) {
+        st = lanes.fork(used);
+        if (st != FDVM_OK) return st;
+    }
     hipError_t e = hipSuccess;
     for (int f = 0; e == hipSuccess && f < nframes; ++f) {
+        const int l = f % used;
+        hipStream_t hs = lanes.stream(l);
+        char *w = static_cast<char *>(ws) + l * fbytes;
+        float *gB = reinterpret_cast<float *>(w);
+        float *P1 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales));
+        float *P2 = reinterpret_cast<float *>(w + 2 * plane_bytes(H, W, nscales));
+        char *inner = w + 3 * plane_bytes(H, W, nscales);
+        double *res = reinterpret_cast<double *>(inner + iir_backward_inner_bytes(H, W, nscales));
+        // the lane's own sigma-gradient sum (first frame of the lane: overwritten)
+        double *gs = used > 1 ? gpart + (int64_t)l * nscales : gsigma;
         const float *gVf = gV + (int64_t)f * v_frame_stride;
         e = launch_laplacian_adjoint(gVf, H, W, pitch, plane_stride, nscales, sig, gB, W, P, hs);
         if (e == hipSuccess && (what & FDVM_GRAD_X)) {
@@ -789,10 +828,13 @@ extern "C" fdvm_status fdvm_iir_laplacian_backward(const void *x, fdvm_dtype dt,
                                       inner, hs);
             if (e == hipSuccess) e = launch_plane_dots(gB, P2, H, W, W, P, nscales, res + nscales, inner, hs);
             if (e == hipSuccess) e = launch_plane_dots(gB, P1, H, W, W, P, nscales, res + 2 * nscales, inner, hs);
-            if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 2, sig, nscales, f > 0, gsigma, hs);
+            if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 2, sig, nscales, f >= used, gs, hs);
         }
     }
-    return from_hip(e);
+    st = lanes.join(from_hip(e));
+    if (st == FDVM_OK && used > 1 && (what & FDVM_GRAD_SIGMA))
+        st = from_hip(launch_sum_lanes(gpart, used, nscales, gsigma, static_cast<hipStream_t>(stream)));
+    return st;
 }
 
 extern "C" fdvm_status fdvm_fir_laplacian_backward(const void *x, fdvm_dtype dt, int64_t H, int64_t W,
@@ -819,20 +861,30 @@ extern "C" fdvm_status fdvm_fir_laplacian_backward(const void *x, fdvm_dtype dt,
             if (h[K + m] != h[K - m]) return FDVM_EINVAL;   // symmetric taps only
     }
     if (ws_bytes < fir_backward_workspace_bytes(H, W, nscales)) return FDVM_ENOMEM;
-    hipStream_t hs = static_cast<hipStream_t>(stream);
     const int64_t P = H * W;
-    char *w = static_cast<char *>(ws);
-    float *gB = reinterpret_cast<float *>(w);
-    float *Q0 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales));
-    float *Q1 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales) + plane_bytes(H, W, 1));
-    float *Q2 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales) + 2 * plane_bytes(H, W, 1));
-    char *rest = w + plane_bytes(H, W, nscales) + 3 * plane_bytes(H, W, 1);
-    double *tab = reinterpret_cast<double *>(rest);
-    char *dots = rest + ((((size_t)std::max(H, W)) * sizeof(double) + 255) & ~(size_t)255);
-    double *res = reinterpret_cast<double *>(dots + dots_workspace_bytes(H, nscales));
+    const size_t fbytes = fir_backward_frame_bytes(H, W, nscales);
+    double *gpart = reinterpret_cast<double *>(static_cast<char *>(ws) + BWD_LANES * fbytes);
+    const int used = std::min(BWD_LANES, nframes);
+    LaneFork lanes(static_cast<hipStream_t>(stream));
+    if (used > 1) {
+        st = lanes.fork(used);
+        if (st != FDVM_OK) return st;
+    }
     const bool rep = bc == FDVM_BC_REPLICATE;
     hipError_t e = hipSuccess;
     for (int f = 0; e == hipSuccess && f < nframes; ++f) {
+        const int l = f % used;
+        hipStream_t hs = lanes.stream(l);
+        char *w = static_cast<char *>(ws) + l * fbytes;
+        float *gB = reinterpret_cast<float *>(w);
+        float *Q0 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales));
+        float *Q1 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales) + plane_bytes(H, W, 1));
+        float *Q2 = reinterpret_cast<float *>(w + plane_bytes(H, W, nscales) + 2 * plane_bytes(H, W, 1));
+        char *rest = w + plane_bytes(H, W, nscales) + 3 * plane_bytes(H, W, 1);
+        double *tab = reinterpret_cast<double *>(rest);
+        char *dots = rest + ((((size_t)std::max(H, W)) * sizeof(double) + 255) & ~(size_t)255);
+        double *res = reinterpret_cast<double *>(dots + dots_workspace_bytes(H, nscales));
+        double *gs = used > 1 ? gpart + (int64_t)l * nscales : gsigma;
         const float *gVf = gV + (int64_t)f * v_frame_stride;
         e = launch_laplacian_adjoint(gVf, H, W, pitch, plane_stride, nscales, sigmas, gB, W, P, hs);
         for (int s = 0; e == hipSuccess && s < nscales; ++s) {
@@ -863,8 +915,11 @@ extern "C" fdvm_status fdvm_fir_laplacian_backward(const void *x, fdvm_dtype dt,
         if (e == hipSuccess && (what & FDVM_GRAD_SIGMA)) {
             e = launch_plane_dots(gVf, V + (int64_t)f * v_frame_stride, H, W, pitch, plane_stride, nscales, res, dots,
                                   hs);
-            if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 1, sigmas, nscales, f > 0, gsigma, hs);
+            if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 1, sigmas, nscales, f >= used, gs, hs);
         }
     }
-    return from_hip(e);
+    st = lanes.join(from_hip(e));
+    if (st == FDVM_OK && used > 1 && (what & FDVM_GRAD_SIGMA))
+        st = from_hip(launch_sum_lanes(gpart, used, nscales, gsigma, static_cast<hipStream_t>(stream)));
+    return st;
 }

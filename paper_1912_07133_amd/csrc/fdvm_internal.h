@@ -140,6 +140,8 @@ hipError_t launch_sum_planes(const float *in, int64_t pitch, int64_t plane, int 
 // (device float64 arrays; sigmas on the host)
 hipError_t launch_gsigma(const double *vv, const double *terms, int nterms, const double *sigmas, int nscales,
                          bool accumulate, double *gsigma, hipStream_t st);
+// out[s] = sum_{l < nlanes} part[l nscales + s] (device float64, lanes in order)
+hipError_t launch_sum_lanes(const double *part, int nlanes, int nscales, double *out, hipStream_t st);
 hipError_t launch_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_t pitch, int64_t plane, int nscales,
                                     const double *sigmas, float *out, int64_t out_pitch, int64_t out_plane,
                                     hipStream_t st);
