@@ -185,11 +185,19 @@ __global__ __launch_bounds__(256) void laplacian_adjoint_kernel(const float *__r
 constexpr int DOT_ROWS = 8;   // rows per partial sum
 constexpr int DOT_T = 256;
 
-__global__ __launch_bounds__(DOT_T) void dots_partial_kernel(const float *__restrict__ a, const float *__restrict__ b,
-                                                             int64_t pitch, int64_t plane, int H, int W,
+// up to three independent sets of inner products in one launch (blockIdx.z:
+// the set); each set as its own launch would compute it
+struct DotSets {
+    const float *a[3], *b[3];
+    int64_t pitch[3], plane[3];
+};
+
+__global__ __launch_bounds__(DOT_T) void dots_partial_kernel(DotSets d, int H, int W, int nscales,
                                                              double *__restrict__ part, int nchunks) {
     __shared__ double red[DOT_T / 64];
-    const int chunk = blockIdx.x, s = blockIdx.y;
+    const int chunk = blockIdx.x, s = blockIdx.y, q = blockIdx.z;
+    const float *a = d.a[q], *b = d.b[q];
+    const int64_t pitch = d.pitch[q], plane = d.plane[q];
     const int y0 = chunk * DOT_ROWS;
     double acc = 0.0;
     for (int y = y0; y < min(H, y0 + DOT_ROWS); ++y) {
@@ -202,10 +210,11 @@ __global__ __launch_bounds__(DOT_T) void dots_partial_kernel(const float *__rest
     if (threadIdx.x == 0) {
         double t = 0.0;
         for (int i = 0; i < DOT_T / 64; ++i) t += red[i];
-        part[(int64_t)s * nchunks + chunk] = t;
+        part[((int64_t)q * nscales + s) * nchunks + chunk] = t;
     }
 }
 
+// out[q nscales + s]: the chunk partials of set q, plane s, summed
 __global__ __launch_bounds__(64) void dots_final_kernel(const double *__restrict__ part, int nchunks,
                                                         double *__restrict__ out) {
     const int s = blockIdx.x;
@@ -321,16 +330,30 @@ size_t dots_workspace_bytes(int64_t H, int nscales) {
     return ((size_t)nscales * nchunks * sizeof(double) + 255) & ~(size_t)255;
 }
 
-hipError_t launch_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch, int64_t plane,
-                             int nscales, double *out, void *ws, hipStream_t st) {
+hipError_t launch_plane_dots_sets(int nsets, const float *const *a, const float *const *b, const int64_t *pitch,
+                                  const int64_t *plane, int64_t H, int64_t W, int nscales, double *out, void *ws,
+                                  hipStream_t st) {
+    if (nsets < 1 || nsets > 3) return hipErrorInvalidValue;
     const int nchunks = (int)((H + DOT_ROWS - 1) / DOT_ROWS);
     double *part = static_cast<double *>(ws);
-    hipLaunchKernelGGL(dots_partial_kernel, dim3((unsigned)nchunks, (unsigned)nscales), dim3(DOT_T), 0, st, a, b,
-                       pitch, plane, (int)H, (int)W, part, nchunks);
+    DotSets d{};
+    for (int q = 0; q < nsets; ++q) {
+        d.a[q] = a[q];
+        d.b[q] = b[q];
+        d.pitch[q] = pitch[q];
+        d.plane[q] = plane[q];
+    }
+    hipLaunchKernelGGL(dots_partial_kernel, dim3((unsigned)nchunks, (unsigned)nscales, (unsigned)nsets), dim3(DOT_T),
+                       0, st, d, (int)H, (int)W, nscales, part, nchunks);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(dots_final_kernel, dim3((unsigned)nscales), dim3(64), 0, st, part, nchunks, out);
+    hipLaunchKernelGGL(dots_final_kernel, dim3((unsigned)(nsets * nscales)), dim3(64), 0, st, part, nchunks, out);
     return hipGetLastError();
+}
+
+hipError_t launch_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch, int64_t plane,
+                             int nscales, double *out, void *ws, hipStream_t st) {
+    return launch_plane_dots_sets(1, &a, &b, &pitch, &plane, H, W, nscales, out, ws, st);
 }
 
 }  // namespace fdvm

@@ -149,7 +149,7 @@ size_t plane_bytes(int64_t H, int64_t W, int n) { return ((size_t)H * W * sizeof
 // column states of the derivative passes, or the inner-product partials.
 size_t iir_backward_inner_bytes(int64_t H, int64_t W, int nscales) {
     const size_t a = iir_cols_workspace_bytes(H, W, nscales, MAX_SECTIONS) + fold_workspace_bytes(H, W, nscales);
-    const size_t b = dots_workspace_bytes(H, nscales);
+    const size_t b = dots_workspace_bytes(H, 3 * nscales);   // the three sets of inner products
     return a > b ? a : b;
 }
 size_t iir_backward_frame_bytes(int64_t H, int64_t W, int nscales) {
@@ -823,11 +823,13 @@ extern "C" fdvm_status fdvm_iir_laplacian_backward(const void *x, fdvm_dtype dt,
             if (e == hipSuccess) e = launch_iir_rows(xf, dt, H, W, x_pitch, P2, W, P, nullptr, 0, dprm, hs);
             if (e == hipSuccess) e = launch_iir_cols(P2, W, P, nullptr, P2, H, W, W, P, false, prm, inner, hs);
             if (e == hipSuccess) e = launch_iir_cols(P1, W, P, nullptr, P1, H, W, W, P, false, dprm, inner, hs);
-            if (e == hipSuccess)
-                e = launch_plane_dots(gVf, V + (int64_t)f * v_frame_stride, H, W, pitch, plane_stride, nscales, res,
-                                      inner, hs);
-            if (e == hipSuccess) e = launch_plane_dots(gB, P2, H, W, W, P, nscales, res + nscales, inner, hs);
-            if (e == hipSuccess) e = launch_plane_dots(gB, P1, H, W, W, P, nscales, res + 2 * nscales, inner, hs);
+            if (e == hipSuccess) {
+                // <gV, V>, <gB, G_y G'_x x>, <gB, G'_y G_x x> into res[0 .. 3 nscales)
+                const float *da[3] = {gVf, gB, gB};
+                const float *db[3] = {V + (int64_t)f * v_frame_stride, P2, P1};
+                const int64_t dp[3] = {pitch, W, W}, dq[3] = {plane_stride, P, P};
+                e = launch_plane_dots_sets(3, da, db, dp, dq, H, W, nscales, res, inner, hs);
+            }
             if (e == hipSuccess) e = launch_gsigma(res, res + nscales, 2, sig, nscales, f >= used, gs, hs);
         }
     }

@@ -148,6 +148,13 @@ hipError_t launch_laplacian_adjoint(const float *g, int64_t H, int64_t W, int64_
 size_t dots_workspace_bytes(int64_t H, int nscales);
 hipError_t launch_plane_dots(const float *a, const float *b, int64_t H, int64_t W, int64_t pitch, int64_t plane,
                              int nscales, double *out, void *ws, hipStream_t st);
+// nsets (1..3) sets of plane inner products in one launch pair: set q pairs
+// a[q] and b[q] (pitch[q], plane stride plane[q]); out[q nscales + s];
+// ws >= dots_workspace_bytes(H, nsets * nscales); each set's sums as
+// launch_plane_dots gives them
+hipError_t launch_plane_dots_sets(int nsets, const float *const *a, const float *const *b, const int64_t *pitch,
+                                  const int64_t *plane, int64_t H, int64_t W, int nscales, double *out, void *ws,
+                                  hipStream_t st);
 
 // FIR blur fused with the normalised Laplacian (float64 accumulation and
 // x-pass plane; ws: fir_laplacian_workspace_bytes)
