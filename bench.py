@@ -419,6 +419,25 @@ def main() -> int:
     stream = torch.cuda.current_stream(dev)
     sp = int(stream.cuda_stream)
 
+    # a plain device copy of known size (256 MiB read + 256 MiB written): its
+    # rate is the practical HBM ceiling the roofline fraction is read against,
+    # and with --calibrate-copy its PMC byte counts scale the counters.  It
+    # runs first, 20 timed copies (≈ 2 ms), before any leg.
+    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ncopy = 20
+    c0.record(stream)
+    for _ in range(ncopy):
+        torch.mul(src, 1.0, out=dst)   # elementwise: reads 256 MiB, writes 256 MiB
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = ncopy * 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    extra_copy = {"bytes_each_way": src.numel() * 4} if args.calibrate_copy else None
+    del src, dst
+
     def check(st, what):
         if st != P.OK:
             raise P.FdvmError(st, what)
@@ -763,24 +782,8 @@ def main() -> int:
         if precision is not None:
             precision_errors(precision, syn, torch, np, log)
 
-    # a plain device copy of known size (256 MiB read + 256 MiB written): its
-    # rate is the practical HBM ceiling the roofline fraction is read against,
-    # and with --calibrate-copy its PMC byte counts scale the counters
-    src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-    dst = torch.empty_like(src)
-    torch.mul(src, 1.0, out=dst)
-    torch.cuda.synchronize()
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(5):
-        torch.mul(src, 1.0, out=dst)   # elementwise: reads 256 MiB, writes 256 MiB
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 1e3) / 1e9
     roofline["measured_copy_GB/s"] = round(copy_gbs, 1)
     roofline["frac_of_copy"] = round(d["GB/s"] / copy_gbs, 4)
-    extra_copy = {"bytes_each_way": src.numel() * 4} if args.calibrate_copy else None
-    del src, dst
 
     out = {
         "metric": "Mpixel·scales/s, IIR vs FIR, at <=1e-5 rel err; % HBM roofline",
