@@ -211,10 +211,13 @@ namespace {
 typedef long double ld;
 const ld PI_L = 3.141592653589793238462643383279502884L;
 
-// S (or, with dsbar, d S / d omega_c) of the K + 1 pair coefficients
+// S (or, with dsbar, d S / d omega_c) of the K + 1 pair coefficients; Sbar
+// depends only on the lag, so its 4 K + 1 values are evaluated once
 template <class F>
 std::vector<ld> pair_matrix(int K, F sbar) {
     const int n = K + 1;
+    std::vector<ld> lag((size_t)(4 * K + 1));
+    for (int d = -2 * K; d <= 2 * K; ++d) lag[(size_t)(d + 2 * K)] = sbar(d);
     std::vector<ld> S((size_t)n * n, 0.0L);
     for (int k1 = 0; k1 < n; ++k1) {
         for (int k2 = 0; k2 < n; ++k2) {
@@ -224,7 +227,7 @@ std::vector<ld> pair_matrix(int K, F sbar) {
                 for (int b = 0; b < s2n; ++b) {
                     const int m1 = a == 0 ? k1 : -k1;
                     const int m2 = b == 0 ? k2 : -k2;
-                    acc += sbar(m1 - m2);
+                    acc += lag[(size_t)(m1 - m2 + 2 * K)];
                 }
             S[(size_t)k1 * n + k2] = acc;
         }
