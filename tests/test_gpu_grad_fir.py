@@ -134,13 +134,17 @@ def test_fir_gradients_against_fp64_reference():
     assert np.max(np.abs(refs - gots)) <= 1e-3 * np.max(np.abs(refs))
 
 
+@pytest.mark.parametrize("nframes", [3, 6])
 @pytest.mark.parametrize("form", ["iir", "fir"])
-def test_batch_equals_frames_one_by_one(form):
-    say(f"case: {form} backward batch of 3 vs frames one by one")
+def test_batch_equals_frames_one_by_one(form, nframes):
+    """The backward call runs the frames on four lanes (frame f on lane f mod
+    4, the sigma gradient summed per lane, then over the lanes): with 6 frames
+    two lanes take two frames each."""
+    say(f"case: {form} backward batch of {nframes} vs frames one by one")
     sig = [2.0, 5.0, 11.0]
-    frames = np.stack([syn.normalised_frame(96, 120, 700 + f, nblobs=4) for f in range(3)]).astype(np.float32)
+    frames = np.stack([syn.normalised_frame(96, 120, 700 + f, nblobs=4) for f in range(nframes)]).astype(np.float32)
     rng = np.random.default_rng(5)
-    gV = torch.from_numpy(rng.standard_normal((3, len(sig), 96, 120)).astype(np.float32)).cuda()
+    gV = torch.from_numpy(rng.standard_normal((nframes, len(sig), 96, 120)).astype(np.float32)).cuda()
     fn = P.iir_laplacian_grad if form == "iir" else P.fir_laplacian_grad
 
     def run(xs, g):
@@ -151,9 +155,9 @@ def test_batch_equals_frames_one_by_one(form):
         return x.grad.cpu().numpy(), st.grad.cpu().numpy(), V.detach().cpu().numpy()
 
     gxb, gsb, Vb = run(frames, gV)
-    assert Vb.shape == (3, len(sig), 96, 120)
+    assert Vb.shape == (nframes, len(sig), 96, 120)
     gs_sum = np.zeros(len(sig))
-    for f in range(3):
+    for f in range(nframes):
         gx1, gs1, V1 = run(frames[f], gV[f])
         assert np.array_equal(V1, Vb[f])
         assert np.array_equal(gx1, gxb[f])     # the same kernels in the same order
