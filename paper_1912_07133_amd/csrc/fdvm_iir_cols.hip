@@ -214,7 +214,7 @@ __device__ __forceinline__ void wait_lds_dma() { asm volatile("s_waitcnt vmcnt(0
 // over all bands but the first records the state entering each band from
 // below; then every band, top first, is swept backwards from its recorded
 // state and finished by the forward sweep, which runs through the whole tile.
-constexpr int FIN_WPB = 4;  // wavefronts (tiles) per final-pass work-group
+constexpr int FIN_WPB = 1;  // wavefronts (tiles) per final-pass work-group (1: measured faster than 2 or 4)
 constexpr int FIN_BLUR = 0, FIN_LAPLACIAN = 1, FIN_HESSIAN = 2;
 
 template <int K, int MODE, bool FX>
